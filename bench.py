@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the local-energy hot path on one MI355X.
+
+One step = the whole path on one batch: local energies of every sample (generator,
+Slater--Condon elements, ansatz on every connected determinant, FP64 ratio sums),
+the weighted energy statistics and the VMC gradient (forward recomputation and
+backward at the samples). Inputs are resident in device memory before timing.
+
+Workload (default): 24 spatial orbitals, 12 alpha + 12 beta electrons, integrals
+with couplings damped by exp(-|p-q|/6), 16384 unique samples with Zipf(1.5)
+multiplicities, ansatz 48 -> 128 -> 128 -> 96 (+ phase) in BF16 on matrix cores with
+FP32 accumulation and FP64 assembly. The all-FP64 path is timed beside it.
+
+Prints one JSON line (see the fields at the bottom).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "local energies/s + H_xx' elems/s at 1 GPU, BF16+FP64 vs all-FP64, |dE|<=1e-5 Ha"
+PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 matrix peak
+PEAK_F64_TFLOPS = 78.6        # MI355X FP64 matrix/vector peak
+COUNTERS = os.path.join(ROOT, "profiles", "eval_bf16_n24_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_07430_amd", "csrc", "made_bf16.hip")
+
+
+def unmasked_weights(n: int, widths) -> int:
+    """Weights the autoregressive mask keeps (degree rule of include/elocal.h), phase head included."""
+    deg_in = np.arange(2 * n) // 2 + 1
+    hid = [np.arange(w) % (n - 1) + 1 for w in widths]
+    total = int(np.sum(hid[0][:, None] >= deg_in[None, :]))
+    for l in range(1, len(widths)):
+        total += int(np.sum(hid[l][:, None] >= hid[l - 1][None, :]))
+    deg_out = np.arange(4 * n) // 4 + 1
+    total += int(np.sum(deg_out[:, None] > hid[-1][None, :]))
+    return total + widths[-1]
+
+
+def dense_weights(n: int, widths) -> int:
+    dims = [2 * n] + list(widths) + [4 * n]
+    return sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1)) + widths[-1]
+
+
+def file_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--cpu-samples", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
+              "(DESIGN.md), not a measured path in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_07430_amd import elocal, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    cfg = 1
+    wl = synth.WORKLOADS[cfg]
+    p = synth.make_problem(cfg)
+    s = p.system
+    B = p.x.shape[0]
+    ham = elocal.Hamiltonian(p.h1e, p.eri, s.n, s.n_alpha, s.n_beta)
+    C = ham.C
+    x = torch.from_numpy(p.x.view(np.int64).copy()).to(dev)
+    w = torch.tensor(p.w, dtype=torch.float64, device=dev)
+    th64 = torch.tensor(p.theta, dtype=torch.float64, device=dev)
+    th16 = th64.to(torch.float32).to(torch.bfloat16).contiguous()
+    ans16 = elocal.Ansatz(s.widths, th16, elocal.BF16)
+    ans64 = elocal.Ansatz(s.widths, th64, elocal.FP64)
+    eloc = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    stats = torch.empty(4, dtype=torch.float64, device=dev)
+    dth = torch.empty(th64.numel(), dtype=torch.float64, device=dev)
+
+    def step(ans):
+        ham.eval(ans, x, out=eloc, want_logpsi=False)
+        ham.grad(ans, x, w, eloc, stats=stats, dtheta=dth)
+
+    def timed(ans, steps, warmup):
+        for _ in range(warmup):
+            step(ans)
+        torch.cuda.synchronize()
+        ham.timing(True)
+        ham.kernel_time(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(ans)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kms, nl = ham.kernel_time(reset=True)
+        ham.timing(False)
+        return (t1 - t0) / steps, kms / max(nl, 1), nl
+
+    sec16, kern16_ms, nl16 = timed(ans16, args.steps, args.warmup)
+    eloc16 = eloc.cpu().numpy().copy()
+    stats16 = stats.cpu().numpy().copy()
+    out = {}
+    if not args.no_fp64:
+        sec64, kern64_ms, nl64 = timed(ans64, args.fp64_steps, 1)
+        eloc64 = eloc.cpu().numpy().copy()
+        out["fp64"] = {
+            "ms_per_step": sec64 * 1e3,
+            "local_energies_per_s": B / sec64,
+            "h_elems_per_s": B * C / sec64,
+            "eval_kernel_ms": kern64_ms,
+            "eval_kernel_tflops_alg": B * (C - 1) * 2 * unmasked_weights(s.n, s.widths) / (kern64_ms * 1e-3) / 1e12,
+            "peak_tflops": PEAK_F64_TFLOPS,
+            "steps": args.fp64_steps,
+        }
+
+    # --- roofline of the dominant kernel (fused BF16 local-energy kernel)
+    uw = unmasked_weights(s.n, s.widths)
+    dw = dense_weights(s.n, s.widths)
+    flops_alg = B * (C - 1) * 2.0 * uw
+    achieved = flops_alg / (kern16_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as f:
+            cnt = json.load(f)
+        if cnt.get("kernel_src_sha256_16") == file_hash(KERNEL_SRC) and cnt.get("samples") == B:
+            traffic = cnt.get("hbm_bytes_per_launch")
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
+            "kernel": "k_eval_bf16", "kernel_ms": kern16_ms, "launches_timed": nl16,
+            "alg_flops_per_row": 2 * uw, "dense_flops_per_row": 2 * dw,
+            "dense_frac": B * (C - 1) * 2.0 * dw / (kern16_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS}
+
+    # --- CPU oracle on a bounded sample (host cores), and the error of both GPU modes on it
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_info
+        from oracle import bf16 as obf16
+        from oracle import energy as oen
+        S = min(args.cpu_samples, B)
+        th_or = obf16.round_to_bf16(p.theta)
+        t0 = time.perf_counter()
+        ref = oen.local_energies(p.h1e, p.eri, s.n, s.n_alpha, s.n_beta, s.widths, th_or, p.x[:S])
+        t1 = time.perf_counter()
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        out["cpu_baseline"] = {"value": S / (t1 - t0), "unit": "local energies/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"first {S} of the {B} samples, BF16-rounded parameters, FP64 NumPy; "
+                                         f"{len(os.sched_getaffinity(0))} host cores visible",
+                               "seconds": t1 - t0}
+        g16 = eloc16[:S, 0] + 1j * eloc16[:S, 1]
+        err = {"samples": S, "bf16_max_abs_dEloc": float(np.max(np.abs(g16 - ref))),
+               "bf16_abs_dE_weighted": float(abs(np.sum(p.w[:S] * g16) / p.w[:S].sum()
+                                                 - np.sum(p.w[:S] * ref) / p.w[:S].sum()))}
+        if not args.no_fp64:
+            S64 = min(8, S)
+            ref64 = oen.local_energies(p.h1e, p.eri, s.n, s.n_alpha, s.n_beta, s.widths, p.theta, p.x[:S64])
+            g64 = eloc64[:S64, 0] + 1j * eloc64[:S64, 1]
+            err["fp64_max_rel_dEloc"] = float(np.max(np.abs(g64 - ref64) / np.abs(ref64)))
+            err["fp64_samples"] = S64
+        out["error_vs_oracle"] = err
+
+    line = {
+        "metric": METRIC,
+        "value": B / sec16,
+        "unit": "local energies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec16 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: n=24 orbitals, 12a+12b, {B} unique samples (Zipf 1.5 weights), "
+                               f"{C} connected determinants each, ansatz 48-128-128-96(+phase)",
+                   "orbitals": s.n, "alpha": s.n_alpha, "beta": s.n_beta, "hidden": list(s.widths),
+                   "samples": B, "connected_per_sample": C, "step": "eval + stats + grad"},
+        "h_elems_per_s": B * C / sec16,
+        "energy": {"re": float(stats16[0]), "im": float(stats16[1]), "var": float(stats16[2])},
+        "roofline": roof,
+    }
+    line.update(out)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * elocal.h -- local energies of the second-quantised electronic Hamiltonian for an
+ * autoregressive neural quantum state, on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (paper: "Scalable Neural Quantum State based Kernel Polynomial
+ * Method for Optical Properties from the First Principle", arXiv 2506.07430):
+ *
+ *   E_loc(x) = sum_{x'} H_{x x'} Psi(x') / Psi(x)             (Results, local-energy
+ *                                                               eq.; Algorithm 1)
+ *   <E>      = sum_i w_i E_loc(x_i) / sum_i w_i               (Methods, batch estimator)
+ *   G        = 2 Re sum_i wbar_i (E_loc(x_i) - <E>) d log Psi*(x_i)
+ *                                                             (Methods, gradient
+ *                                                               estimator, baseline <E>)
+ *
+ * for a batch of B unique occupation bitstrings x_i with multiplicities w_i. H is the
+ * Hamiltonian of the Methods section built from one- and two-body integrals;
+ * Psi = exp(A + i phi) is the masked autoregressive ansatz of the Results section.
+ * The x' run over x and all its single and double excitations, enumerated in a fixed
+ * canonical order (see elocal_connect).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Spin-orbitals: k = 2p + s for spatial orbital p (0-based) and spin s (0 = alpha/up,
+ *   1 = beta/down) -- the paper's qubits 2i-1, 2i, made 0-based.
+ * Bitstrings: W = ceil(2 n_orb / 64) little-endian uint64 words per determinant;
+ *   spin-orbital k is bit (k % 64) of word (k / 64); unused high bits must be 0.
+ * Signs: |x> = a+_{k1} a+_{k2} ... |vac> with k1 < k2 < ...; a_k and a+_k carry
+ *   (-1)^(number of occupied spin-orbitals below k) (the Jordan--Wigner string).
+ * Integrals: spatial, chemists' order, FP64, row-major:
+ *   h1e[p*n + q] = h_pq, eri[((p*n + q)*n + r)*n + s] = (pq|rs), with
+ *   H = sum_{pq,s} h_pq a+_{ps} a_{qs} + 1/2 sum_{pqrs,st} (pq|rs) a+_{ps} a+_{rt} a_{st} a_{qs}.
+ *   eri must have the 8-fold permutational symmetry of real orbitals.
+ * Ansatz parameters: one flat vector theta (layout at elocal_ansatz below).
+ * Memory: every pointer argument of the compute calls is DEVICE memory owned by the
+ *   caller; the library allocates nothing per call (all scratch lives in the
+ *   caller's workspace). elocal_create copies the integrals (host pointers) to device
+ *   memory owned by the handle.
+ * Streams: compute calls only enqueue work on the given stream (NULL = the default
+ *   stream) and return; they never synchronise, except elocal_check_samples.
+ * Errors: every call returns elocal_status; a non-zero status leaves the outputs
+ *   unspecified and the handle usable. elocal_last_error() gives a message for the
+ *   calling thread's last failure.
+ * Threads: a handle is read-only after elocal_create (except for the timing calls at
+ *   the end of this file); concurrent calls on one handle with separate workspaces
+ *   and outputs are allowed.
+ */
+#ifndef ELOCAL_H
+#define ELOCAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ELOCAL_OK = 0,
+  ELOCAL_E_INVALID = 1,     /* bad argument: null pointer, size out of range, ...        */
+  ELOCAL_E_CONFIG = 2,      /* a bitstring is not in the (n_alpha, n_beta) sector        */
+  ELOCAL_E_WORKSPACE = 3,   /* workspace smaller than elocal_workspace_bytes()           */
+  ELOCAL_E_NOMEM = 4,       /* device allocation in elocal_create failed                 */
+  ELOCAL_E_DEVICE = 5,      /* HIP runtime error, or no gfx950 device is current         */
+  ELOCAL_E_UNSUPPORTED = 6  /* shape outside what the kernels handle                     */
+} elocal_status;
+
+/* Arithmetic of the ansatz. H_{xx'}, ratios and every sum stay FP64 in both modes. */
+enum {
+  ELOCAL_FP64 = 0,  /* theta is double; ansatz on FP64 matrix cores                      */
+  ELOCAL_BF16 = 1   /* theta is bfloat16 (uint16 bit patterns); ansatz GEMMs on BF16
+                       matrix cores with FP32 accumulation, activations carried as a
+                       hi+lo pair of bfloat16 values                                      */
+};
+
+/* Operations, for elocal_workspace_bytes. */
+enum { ELOCAL_OP_CONNECT = 0, ELOCAL_OP_EVAL = 1, ELOCAL_OP_GRAD = 2 };
+
+typedef struct elocal_ctx* elocal_t;
+typedef void* elocal_stream;   /* a hipStream_t */
+
+/*
+ * Ansatz description (host struct; theta itself is device memory).
+ *
+ * The network (Results, wavefunction ansatz; Fig. 1b): inputs are the 2n occupation
+ * bits as 0/1; n_hidden >= 1 masked dense layers with ReLU; an output layer of 4n
+ * logits ordered [orbital p][state s], s = x_{2p} + 2 x_{2p+1}; a phase head
+ * phi = 2 pi sigmoid(w_phi . h_last + b_phi). Degrees: input bit k has degree
+ * k/2 + 1; hidden unit j has degree (j mod (n-1)) + 1; a weight is used only if
+ * input->hidden m >= d, hidden->hidden m' >= m, hidden->output(orbital p) p + 1 > m;
+ * weights outside this mask are ignored (read as 0) and get gradient exactly 0.
+ * Orbital p's 4 logits are restricted to the occupations that keep both electron
+ * counts reachable (Results, number-conserving conditionals) and renormalised by a
+ * softmax; A(x) = 1/2 sum_p log p_p(s_p).
+ *
+ * Flat layout of theta (P entries, P = elocal_num_params): for l = 0..n_hidden (the
+ * last is the output layer) W_l[out_l][in_l] row-major then b_l[out_l], with
+ * in_0 = 2n, out_l = widths[l] (l < n_hidden), out_{n_hidden} = 4n; then
+ * w_phi[widths[n_hidden-1]], then b_phi[1].
+ * Supported: 2 <= n <= 64, 1 <= n_hidden <= 8, every width a multiple of 32 in
+ * [32, 256].
+ */
+typedef struct {
+  int n_hidden;
+  const int* widths;   /* host array [n_hidden]                                  */
+  int precision;       /* ELOCAL_FP64 (theta: double) or ELOCAL_BF16 (theta: uint16) */
+  const void* theta;   /* device pointer, P entries                              */
+} elocal_ansatz;
+
+/* Create a handle for one Hamiltonian and electron count (synchronous).
+ * h1e [n*n], eri [n^4]: HOST pointers, copied. n_orb in [2, 64]; 0 <= n_alpha,
+ * n_beta <= n_orb. Fails with ELOCAL_E_DEVICE when no gfx950 device is current. */
+elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int n_alpha,
+                            int n_beta, elocal_t* out);
+elocal_status elocal_destroy(elocal_t h);
+
+/* Number of connected determinants per sample, diagonal included (closed form):
+ * C = 1 + sum_s n_s v_s + sum_s C(n_s,2) C(v_s,2) + n_a v_a n_b v_b, v_s = n - n_s.
+ * Returns -1 for a null handle. No device work. */
+int64_t elocal_num_connected(elocal_t h);
+/* Words per bitstring, W = ceil(2n/64). */
+int elocal_words(elocal_t h);
+/* Length P of theta for n_orb and the hidden widths; -1 if unsupported. */
+int64_t elocal_num_params(int n_orb, int n_hidden, const int* widths);
+
+/* Bytes of device workspace a call needs (op = ELOCAL_OP_*; `a` may be NULL for
+ * ELOCAL_OP_CONNECT). 0 on invalid arguments (elocal_last_error says why). */
+size_t elocal_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B, int op);
+
+/*
+ * Materialised connected lists (Results: the coupled configurations x^p of Algorithm 1,
+ * here enumerated as fermionic excitations of x instead of Pauli flips).
+ * x [B][W] in; out, for t in [0, C), in canonical order:
+ *   xp   [B][C][W]  the determinant x'_t;
+ *   hval [B][C]     H_{x'_t x} (FP64; sign included);
+ *   sign [B][C]     <x'_t| a+_a a+_b a_j a_i |x> (+1/-1; +1 for the diagonal);
+ *   exc  [B][C]     spin-orbitals i | j<<8 | a<<16 | b<<24, 0xFF for unused slots.
+ * Order: t=0 the diagonal; alpha singles (i over occupied alpha ascending, outer;
+ * a over virtual alpha ascending); beta singles; alpha-alpha doubles (occupied pairs
+ * i<j lexicographic, outer x virtual pairs a<b lexicographic); beta-beta doubles;
+ * alpha-beta doubles ((i,a) in alpha-single order, outer x (j,b) in beta-single
+ * order). Values: diagonal sum_k h_kk + 1/2 sum_kl [(kk|ll) - (kl|lk)]; single
+ * h_ai + sum_k [(ai|kk) - (ak|ki)]; double (ai|bj) - (aj|bi) (spin-orbital integrals).
+ * Samples must be in the sector (unchecked here; see elocal_check_samples).
+ */
+elocal_status elocal_connect(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B,
+                             void* ws, size_t ws_bytes, uint64_t* xp, double* hval,
+                             int8_t* sign, uint32_t* exc);
+
+/*
+ * Local energies (Results, local-energy eq. and Algorithm 1; Methods, l_theta).
+ * x [B][W] in; eloc [B][2] out (re, im); logpsi [B][2] out (A = log|Psi|, phi), may be
+ * NULL. Every x' of the canonical list of every sample is generated, its matrix
+ * element formed in FP64, the ansatz evaluated on it, and H_{xx'} exp(A'-A+i(phi'-phi))
+ * summed in FP64 in a fixed order (bitwise repeatable).
+ */
+elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a,
+                          const uint64_t* x, int64_t B, void* ws, size_t ws_bytes,
+                          double* eloc, double* logpsi);
+
+/*
+ * Energy statistics (Methods, batch estimator): stats[4] = (Re<E>, Im<E>,
+ * sum_i w_i |E_i - <E>|^2 / sum_i w_i, sum_i w_i), from eloc [B][2] and w [B]
+ * (device). B >= 1; sum w must be > 0. Fixed-order FP64 reduction.
+ */
+elocal_status elocal_stats(elocal_stream s, const double* eloc, const double* w, int64_t B,
+                           double* stats);
+
+/*
+ * VMC gradient (Methods, gradient estimator with baseline b = <E>):
+ *   dtheta = 2 sum_i wbar_i [Re(E_i - <E>) dA_i + Im(E_i - <E>) dphi_i],  wbar = w / sum w,
+ * with <E> complex and held fixed; the ansatz forward at the B samples is recomputed
+ * (nothing is kept from elocal_eval) and differentiated by hand in FP64. Inputs: x
+ * [B][W], w [B], eloc [B][2] (from elocal_eval); outputs: stats [4] as elocal_stats,
+ * dtheta [P] (double, theta's layout; masked weights get exactly 0).
+ */
+elocal_status elocal_grad(elocal_t h, elocal_stream s, const elocal_ansatz* a,
+                          const uint64_t* x, const double* w, const double* eloc, int64_t B,
+                          void* ws, size_t ws_bytes, double* stats, double* dtheta);
+
+/*
+ * Optional input check: counts samples of x [B][W] whose alpha/beta popcounts differ
+ * from (n_alpha, n_beta) or whose unused high bits are set. Synchronises the stream.
+ * Returns ELOCAL_E_CONFIG if any sample is bad (*n_bad, host, gets the count).
+ * Needs a workspace of at least 8 bytes.
+ */
+elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B,
+                                   void* ws, size_t ws_bytes, int64_t* n_bad);
+
+/*
+ * Timing of the dominant kernel (the fused local-energy kernel of elocal_eval).
+ * When enabled, each elocal_eval on the handle records a pair of HIP events around
+ * that kernel on the caller's stream (a ring of 1024 pairs, reused in order).
+ * elocal_kernel_timing waits for the recorded events, returns the summed milliseconds
+ * and the number of launches recorded since the last reset (reset != 0 clears them).
+ * These two calls mutate the handle: do not overlap them with other calls on it.
+ */
+elocal_status elocal_timing_enable(elocal_t h, int on);
+elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launches, int reset);
+
+/* Message for the calling thread's last failure ("" if none). */
+const char* elocal_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELOCAL_H */

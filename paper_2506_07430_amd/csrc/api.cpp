@@ -1,0 +1,547 @@
+// C ABI of libelocal: argument checks, workspace layout, kernel sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/elocal.h"
+#include "elocal_internal.hpp"
+#include "kernels.hpp"
+
+using namespace elocal;
+
+namespace {
+
+thread_local std::string g_err;
+
+elocal_status fail(elocal_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+elocal_status hip_fail(hipError_t e, const char* what) {
+  return fail(ELOCAL_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                     \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+int64_t binom2(int64_t m) { return m * (m - 1) / 2; }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Bump allocator over the caller's workspace.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? (T*)(base + off) : nullptr;
+    off = align256(off + count * sizeof(T));
+    return p;
+  }
+};
+
+bool is_gfx950(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+}  // namespace
+
+struct elocal_ctx {
+  int dev = 0;
+  SysDev sys{};
+  double* d_h1e = nullptr;
+  double* d_S = nullptr;
+  double* d_J2 = nullptr;
+  double* d_K2 = nullptr;
+  double* d_J3 = nullptr;
+  double* d_K3 = nullptr;
+  uint16_t* d_pairs = nullptr;
+  int cu_count = 256;
+  // optional timing of the fused kernel
+  static constexpr int kRing = 1024;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int64_t recorded = 0;   // pairs recorded since the last reset
+  int64_t ring_pos = 0;
+};
+
+namespace {
+
+struct AnsatzGeom {
+  MadeDev md{};
+  ThetaLayout T{};
+  int hmax = 0;
+  int precision = 0;
+  size_t wbytes = 0, bbytes = 0;
+};
+
+elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom& G) {
+  if (!a) return fail(ELOCAL_E_INVALID, "ansatz descriptor is null");
+  const int n = h->sys.n;
+  if (a->n_hidden < 1 || a->n_hidden > kMaxHidden)
+    return fail(ELOCAL_E_UNSUPPORTED, "n_hidden=%d outside [1, %d]", a->n_hidden, kMaxHidden);
+  if (!a->widths) return fail(ELOCAL_E_INVALID, "widths is null");
+  if (a->precision != ELOCAL_FP64 && a->precision != ELOCAL_BF16)
+    return fail(ELOCAL_E_INVALID, "precision=%d is neither ELOCAL_FP64 nor ELOCAL_BF16", a->precision);
+  const int L = a->n_hidden;
+  int wmax = 0;
+  for (int l = 0; l < L; ++l) {
+    const int w = a->widths[l];
+    if (w < 32 || w > 256 || w % 32)
+      return fail(ELOCAL_E_UNSUPPORTED, "hidden width %d is not a multiple of 32 in [32, 256]", w);
+    wmax = std::max(wmax, w);
+  }
+  G.hmax = wmax <= 32 ? 32 : wmax <= 64 ? 64 : wmax <= 128 ? 128 : 256;
+  G.precision = a->precision;
+  MadeDev& M = G.md;
+  M.n = n;
+  M.L = L;
+  uint32_t wo = 0, bo = 0;
+  for (int l = 0; l <= L; ++l) {
+    M.nin[l] = (l == 0) ? 2 * n : a->widths[l - 1];
+    M.nout[l] = (l == L) ? 4 * n + 1 : a->widths[l];
+    M.nk[l] = (a->precision == ELOCAL_BF16) ? (M.nin[l] + 31) / 32 : (M.nin[l] + 3) / 4;
+    M.nob[l] = (M.nout[l] + 15) / 16;
+    M.woff[l] = wo;
+    M.boff[l] = bo;
+    wo += (uint32_t)(M.nob[l] * M.nk[l]);
+    bo += (uint32_t)(16 * M.nob[l]);
+  }
+  M.nfrag = wo;
+  M.nbias = bo;
+  G.wbytes = (size_t)wo * 64 * (a->precision == ELOCAL_BF16 ? 16 : 8);
+  G.bbytes = (size_t)bo * (a->precision == ELOCAL_BF16 ? 4 : 8);
+  // caller's flat layout
+  uint32_t off = 0;
+  for (int l = 0; l <= L; ++l) {
+    const int out = (l == L) ? 4 * n : a->widths[l];
+    G.T.offW[l] = off;
+    off += (uint32_t)(out * M.nin[l]);
+    G.T.offb[l] = off;
+    off += (uint32_t)out;
+  }
+  G.T.offwphi = off;
+  off += (uint32_t)a->widths[L - 1];
+  G.T.offbphi = off;
+  off += 1;
+  G.T.P = off;
+  return ELOCAL_OK;
+}
+
+// Work decomposition of the fused evaluation.
+struct EvalPlan {
+  uint32_t rows_per_tile, tpi, ips;
+  int64_t n_items;
+  bool ldsw;
+  size_t lds;
+  unsigned grid;
+};
+
+EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
+  EvalPlan p{};
+  p.rows_per_tile = (G.precision == ELOCAL_BF16) ? 32 : 16;
+  p.tpi = 16;
+  const uint64_t rows = h->sys.C - 1;   // the diagonal entry needs no ansatz call
+  const uint64_t per_item = (uint64_t)p.rows_per_tile * p.tpi;
+  p.ips = (uint32_t)((rows + per_item - 1) / per_item);
+  p.n_items = (int64_t)p.ips * B;
+  if (G.precision == ELOCAL_BF16) {
+    const size_t ctx = 4 * (sizeof(SampleCtx) + kMaxOrb * sizeof(float));
+    const size_t need = align256(G.wbytes) + align256(G.bbytes) + ctx;
+    p.ldsw = need <= 81920;   // two 4-wave blocks per CU (160 KiB LDS)
+    p.lds = p.ldsw ? need : ctx;
+  } else {
+    p.ldsw = false;
+    p.lds = 0;
+  }
+  const int64_t want = (p.n_items + 3) / 4;
+  const int64_t cap = (int64_t)h->cu_count * 8;
+  p.grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
+  return p;
+}
+
+struct EvalWs {
+  double* ediag;
+  double* F;
+  void* frag;
+  void* bias;
+  float* lpx;
+  double* lpx64;
+  double* zphi;
+  double* partial;
+  size_t bytes;
+};
+
+EvalWs carve_eval(const elocal_ctx* h, const AnsatzGeom& G, const EvalPlan& p, int64_t B, void* ws) {
+  Carve c(ws);
+  EvalWs w{};
+  const size_t nS = h->sys.nSa + h->sys.nSb;
+  w.ediag = c.take<double>(std::max<int64_t>(B, 1));
+  w.F = c.take<double>(std::max<size_t>((size_t)B * nS, 1));
+  w.frag = c.take<char>(G.wbytes);
+  w.bias = c.take<char>(G.bbytes);
+  if (G.precision == ELOCAL_BF16) {
+    w.lpx = c.take<float>(std::max<size_t>((size_t)B * h->sys.n, 1));
+    w.lpx64 = nullptr;
+  } else {
+    w.lpx = nullptr;
+    w.lpx64 = c.take<double>(std::max<size_t>((size_t)B * h->sys.n, 1));
+  }
+  w.zphi = c.take<double>(std::max<int64_t>(B, 1));
+  w.partial = c.take<double>(std::max<size_t>((size_t)p.n_items * 2, 1));
+  w.bytes = c.off;
+  return w;
+}
+
+struct ConnectWs {
+  double* ediag;
+  double* F;
+  size_t bytes;
+};
+
+ConnectWs carve_connect(const elocal_ctx* h, int64_t B, void* ws) {
+  Carve c(ws);
+  ConnectWs w{};
+  const size_t nS = h->sys.nSa + h->sys.nSb;
+  w.ediag = c.take<double>(std::max<int64_t>(B, 1));
+  w.F = c.take<double>(std::max<size_t>((size_t)B * nS, 1));
+  w.bytes = c.off;
+  return w;
+}
+
+size_t carve_grad(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, void* ws, GradPlan* out) {
+  Carve c(ws);
+  GradPlan P{};
+  const int L = G.md.L, n = h->sys.n;
+  P.n = n; P.na = h->sys.na; P.nb = h->sys.nb; P.L = L;
+  P.dims[0] = 2 * n;
+  for (int l = 0; l < L; ++l) P.dims[l + 1] = G.md.nout[l];
+  P.dims[L + 1] = 4 * n + 1;
+  int maxdim = 0;
+  size_t maxw = 0;
+  for (int l = 0; l <= L + 1; ++l) maxdim = std::max(maxdim, P.dims[l]);
+  for (int l = 0; l <= L; ++l) {
+    const size_t cnt = (size_t)P.dims[l + 1] * P.dims[l];
+    maxw = std::max(maxw, cnt);
+    P.Wm[l] = c.take<double>(cnt);
+    P.bm[l] = c.take<double>(P.dims[l + 1]);
+    P.dW[l] = c.take<double>(cnt);
+    P.db[l] = c.take<double>(P.dims[l + 1]);
+  }
+  const size_t Bs = (size_t)std::max<int64_t>(B, 1);
+  for (int l = 0; l <= L + 1; ++l) P.h[l] = c.take<double>(Bs * P.dims[l]);
+  P.d0 = c.take<double>(Bs * maxdim);
+  P.d1 = c.take<double>(Bs * maxdim);
+  P.ones = c.take<double>(Bs);
+  P.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, B / 256));
+  P.part = c.take<double>((size_t)P.splits * maxw);
+  P.T = G.T;
+  P.precision = G.precision;
+  if (out) *out = P;
+  return c.off;
+}
+
+SysDev build_sys(int n, int na, int nb) {
+  SysDev s{};
+  s.n = n; s.na = na; s.nb = nb; s.va = n - na; s.vb = n - nb;
+  s.W = (2 * n + 63) / 64;
+  s.nSa = (uint32_t)(na * s.va);
+  s.nSb = (uint32_t)(nb * s.vb);
+  s.npo_a = (uint32_t)binom2(na); s.npv_a = (uint32_t)binom2(s.va);
+  s.npo_b = (uint32_t)binom2(nb); s.npv_b = (uint32_t)binom2(s.vb);
+  s.nDaa = s.npo_a * s.npv_a;
+  s.nDbb = s.npo_b * s.npv_b;
+  s.nDab = s.nSa * s.nSb;
+  s.C = 1u + s.nSa + s.nSb + s.nDaa + s.nDbb + s.nDab;
+  return s;
+}
+
+elocal_status check_device(const elocal_ctx* h) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != h->dev) return fail(ELOCAL_E_DEVICE, "current device %d is not the handle's device %d", dev, h->dev);
+  return ELOCAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* elocal_last_error(void) { return g_err.c_str(); }
+
+int64_t elocal_num_params(int n_orb, int n_hidden, const int* widths) {
+  if (n_orb < 2 || n_orb > kMaxOrb || n_hidden < 1 || n_hidden > kMaxHidden || !widths) return -1;
+  int64_t p = 0;
+  int in = 2 * n_orb;
+  for (int l = 0; l < n_hidden; ++l) {
+    if (widths[l] < 1) return -1;
+    p += (int64_t)widths[l] * in + widths[l];
+    in = widths[l];
+  }
+  p += (int64_t)4 * n_orb * in + 4 * n_orb;
+  p += in + 1;
+  return p;
+}
+
+elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int n_alpha, int n_beta,
+                            elocal_t* out) {
+  if (!out) return fail(ELOCAL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!h1e || !eri) return fail(ELOCAL_E_INVALID, "h1e or eri is null");
+  if (n_orb < 2 || n_orb > kMaxOrb) return fail(ELOCAL_E_UNSUPPORTED, "n_orb=%d outside [2, %d]", n_orb, kMaxOrb);
+  if (n_alpha < 0 || n_beta < 0 || n_alpha > n_orb || n_beta > n_orb)
+    return fail(ELOCAL_E_INVALID, "electron counts (%d, %d) outside [0, n_orb=%d]", n_alpha, n_beta, n_orb);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) return fail(ELOCAL_E_DEVICE, "no HIP device available");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (!is_gfx950(dev)) return fail(ELOCAL_E_DEVICE, "device %d is not gfx950", dev);
+  elocal_ctx* h = new elocal_ctx();
+  h->dev = dev;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      h->cu_count = prop.multiProcessorCount;
+  }
+  h->sys = build_sys(n_orb, n_alpha, n_beta);
+  const size_t n = n_orb, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  // pair tables for m = n_alpha, n - n_alpha, n_beta, n - n_beta
+  const int ms[4] = {n_alpha, n_orb - n_alpha, n_beta, n_orb - n_beta};
+  std::vector<uint16_t> pairs;
+  size_t poff[4];
+  for (int t = 0; t < 4; ++t) {
+    poff[t] = pairs.size();
+    for (int i = 0; i < ms[t]; ++i)
+      for (int j = i + 1; j < ms[t]; ++j) pairs.push_back((uint16_t)(i | (j << 8)));
+  }
+  if (pairs.empty()) pairs.push_back(0);
+  double* d_eri = nullptr;
+  auto cleanup = [&](elocal_status st) {
+    hipFree(d_eri);
+    hipFree(h->d_h1e); hipFree(h->d_S); hipFree(h->d_J2); hipFree(h->d_K2);
+    hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs);
+    delete h;
+    return st;
+  };
+  if (hipMalloc(&h->d_h1e, n2 * 8) != hipSuccess || hipMalloc(&d_eri, n4 * 8) != hipSuccess ||
+      hipMalloc(&h->d_S, n4 * 8) != hipSuccess || hipMalloc(&h->d_J2, n2 * 8) != hipSuccess ||
+      hipMalloc(&h->d_K2, n2 * 8) != hipSuccess || hipMalloc(&h->d_J3, n3 * 8) != hipSuccess ||
+      hipMalloc(&h->d_K3, n3 * 8) != hipSuccess ||
+      hipMalloc(&h->d_pairs, pairs.size() * sizeof(uint16_t)) != hipSuccess)
+    return cleanup(fail(ELOCAL_E_NOMEM, "device allocation failed in elocal_create"));
+  hipError_t err = hipMemcpy(h->d_h1e, h1e, n2 * 8, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(d_eri, eri, n4 * 8, hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(h->d_pairs, pairs.data(), pairs.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = launch_build_tables(n_orb, d_eri, h->d_S, h->d_J2, h->d_K2, h->d_J3, h->d_K3, nullptr);
+  if (err == hipSuccess) err = hipDeviceSynchronize();
+  if (err != hipSuccess) return cleanup(hip_fail(err, "elocal_create"));
+  hipFree(d_eri);
+  d_eri = nullptr;
+  SysDev& s = h->sys;
+  s.h1e = h->d_h1e; s.S = h->d_S; s.J2 = h->d_J2; s.K2 = h->d_K2; s.J3 = h->d_J3; s.K3 = h->d_K3;
+  s.pair_oa = h->d_pairs + poff[0];
+  s.pair_va = h->d_pairs + poff[1];
+  s.pair_ob = h->d_pairs + poff[2];
+  s.pair_vb = h->d_pairs + poff[3];
+  *out = h;
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_destroy(elocal_t h) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  for (hipEvent_t e : h->ev_start) hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_stop) hipEventDestroy(e);
+  hipFree(h->d_h1e); hipFree(h->d_S); hipFree(h->d_J2); hipFree(h->d_K2);
+  hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs);
+  delete h;
+  return ELOCAL_OK;
+}
+
+int64_t elocal_num_connected(elocal_t h) { return h ? (int64_t)h->sys.C : -1; }
+
+int elocal_words(elocal_t h) { return h ? h->sys.W : -1; }
+
+size_t elocal_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B, int op) {
+  if (!h) { fail(ELOCAL_E_INVALID, "handle is null"); return 0; }
+  if (B < 0) { fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B); return 0; }
+  if (op == ELOCAL_OP_CONNECT) return carve_connect(h, B, nullptr).bytes;
+  AnsatzGeom G;
+  if (make_geom(h, a, G) != ELOCAL_OK) return 0;
+  if (op == ELOCAL_OP_EVAL) {
+    const EvalPlan p = plan_eval(h, G, B);
+    return carve_eval(h, G, p, B, nullptr).bytes;
+  }
+  if (op == ELOCAL_OP_GRAD) return carve_grad(h, G, B, nullptr, nullptr);
+  fail(ELOCAL_E_INVALID, "unknown op %d", op);
+  return 0;
+}
+
+elocal_status elocal_connect(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B, void* ws,
+                             size_t ws_bytes, uint64_t* xp, double* hval, int8_t* sign, uint32_t* exc) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (B < 0) return fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B);
+  if (B == 0) return ELOCAL_OK;
+  if (!x || !ws || !xp || !hval || !sign || !exc) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  const ConnectWs need = carve_connect(h, B, nullptr);
+  if (ws_bytes < need.bytes)
+    return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const ConnectWs w = carve_connect(h, B, ws);
+  hipStream_t st = (hipStream_t)s;
+  HIP_TRY(launch_prep(h->sys, x, B, w.ediag, w.F, st), "prep launch");
+  HIP_TRY(launch_connect(h->sys, x, B, w.ediag, w.F, xp, hval, sign, exc, st), "connect launch");
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x, int64_t B,
+                          void* ws, size_t ws_bytes, double* eloc, double* logpsi) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  AnsatzGeom G;
+  if (elocal_status e = make_geom(h, a, G)) return e;
+  if (B < 0) return fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B);
+  if (B == 0) return ELOCAL_OK;
+  if (!a->theta || !x || !ws || !eloc) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  const EvalPlan p = plan_eval(h, G, B);
+  const EvalWs need = carve_eval(h, G, p, B, nullptr);
+  if (ws_bytes < need.bytes)
+    return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const EvalWs w = carve_eval(h, G, p, B, ws);
+  hipStream_t st = (hipStream_t)s;
+  MadeDev M = G.md;
+  M.wfrag = w.frag;
+  M.bias = w.bias;
+  if (G.precision == ELOCAL_BF16)
+    HIP_TRY(launch_pack_bf16(M, G.T, (const uint16_t*)a->theta, w.frag, (float*)w.bias, st), "pack launch");
+  else
+    HIP_TRY(launch_pack_f64(M, G.T, (const double*)a->theta, w.frag, (double*)w.bias, st), "pack launch");
+  HIP_TRY(launch_prep(h->sys, x, B, w.ediag, w.F, st), "prep launch");
+  RowsArgs R{};
+  R.sys = h->sys; R.made = M; R.x = x; R.B = B; R.lpx = w.lpx; R.lpx64 = w.lpx64; R.zphi = w.zphi;
+  R.logpsi = logpsi;
+  if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, st), "sample pass launch");
+  else HIP_TRY(launch_rows_f64(R, G.hmax, st), "sample pass launch");
+  EvalArgs E{};
+  E.sys = h->sys; E.made = M; E.x = x; E.B = B; E.ediag = w.ediag; E.F = w.F; E.lpx = w.lpx;
+  E.lpx64 = w.lpx64; E.zphi = w.zphi; E.partial = w.partial; E.n_items = p.n_items; E.ips = p.ips;
+  E.tpi = p.tpi;
+  const bool timed = h->timing && p.n_items > 0;
+  const int slot = (int)(h->ring_pos % elocal_ctx::kRing);
+  if (timed) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
+  if (G.precision == ELOCAL_BF16) {
+    if (p.ldsw) {
+      E.lds_bias_off = (uint32_t)align256(G.wbytes);
+      E.lds_ctx_off = (uint32_t)(align256(G.wbytes) + align256(G.bbytes));
+    } else {
+      E.lds_bias_off = 0;
+      E.lds_ctx_off = 0;
+    }
+    HIP_TRY(launch_eval_bf16(E, G.hmax, p.ldsw, p.lds, p.grid, st), "eval launch");
+  } else {
+    HIP_TRY(launch_eval_f64(E, G.hmax, p.grid, st), "eval launch");
+  }
+  if (timed) {
+    HIP_TRY(hipEventRecord(h->ev_stop[slot], st), "timing event");
+    h->ring_pos++;
+    h->recorded++;
+  }
+  HIP_TRY(launch_reduce(w.ediag, w.partial, B, p.ips, eloc, st), "reduce launch");
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_stats(elocal_stream s, const double* eloc, const double* w, int64_t B, double* stats) {
+  if (B < 1) return fail(ELOCAL_E_INVALID, "B=%lld < 1", (long long)B);
+  if (!eloc || !w || !stats) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  HIP_TRY(launch_stats(eloc, w, B, stats, (hipStream_t)s), "stats launch");
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_grad(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x,
+                          const double* w, const double* eloc, int64_t B, void* ws, size_t ws_bytes,
+                          double* stats, double* dtheta) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  AnsatzGeom G;
+  if (elocal_status e = make_geom(h, a, G)) return e;
+  if (B < 1) return fail(ELOCAL_E_INVALID, "B=%lld < 1", (long long)B);
+  if (!a->theta || !x || !w || !eloc || !ws || !stats || !dtheta)
+    return fail(ELOCAL_E_INVALID, "null pointer argument");
+  const size_t need = carve_grad(h, G, B, nullptr, nullptr);
+  if (ws_bytes < need) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if (elocal_status st = check_device(h)) return st;
+  GradPlan P;
+  carve_grad(h, G, B, ws, &P);
+  P.theta = a->theta; P.x = x; P.w = w; P.eloc = eloc; P.B = B; P.stats = stats; P.dtheta = dtheta;
+  HIP_TRY(launch_grad(P, (hipStream_t)s), "grad launch");
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_timing_enable(elocal_t h, int on) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (on && h->ev_start.empty()) {
+    h->ev_start.resize(elocal_ctx::kRing);
+    h->ev_stop.resize(elocal_ctx::kRing);
+    for (int i = 0; i < elocal_ctx::kRing; ++i) {
+      HIP_TRY(hipEventCreate(&h->ev_start[i]), "hipEventCreate");
+      HIP_TRY(hipEventCreate(&h->ev_stop[i]), "hipEventCreate");
+    }
+  }
+  h->timing = on != 0;
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launches, int reset) {
+  if (!h || !total_ms || !launches) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  const int64_t n = std::min<int64_t>(h->recorded, elocal_ctx::kRing);
+  double tot = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int slot = (int)((h->ring_pos - 1 - i + elocal_ctx::kRing * 4) % elocal_ctx::kRing);
+    HIP_TRY(hipEventSynchronize(h->ev_stop[slot]), "hipEventSynchronize");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev_start[slot], h->ev_stop[slot]), "hipEventElapsedTime");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = n;
+  if (reset) h->recorded = 0;
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B, void* ws,
+                                   size_t ws_bytes, int64_t* n_bad) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (B < 0) return fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B);
+  if ((B > 0 && !x) || !ws) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  if (ws_bytes < 8) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < 8 needed", ws_bytes);
+  if (elocal_status st = check_device(h)) return st;
+  hipStream_t st = (hipStream_t)s;
+  unsigned long long* bad = (unsigned long long*)ws;
+  HIP_TRY(launch_check(h->sys, x, B, bad, st), "check launch");
+  unsigned long long hbad = 0;
+  HIP_TRY(hipMemcpyAsync(&hbad, bad, 8, hipMemcpyDeviceToHost, st), "check copy");
+  HIP_TRY(hipStreamSynchronize(st), "check sync");
+  if (n_bad) *n_bad = (int64_t)hbad;
+  if (hbad) return fail(ELOCAL_E_CONFIG, "%llu sample(s) not in the (%d, %d) sector", hbad, h->sys.na, h->sys.nb);
+  return ELOCAL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// Internal definitions shared by the HIP translation units of libelocal.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace elocal {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxOrb = 64;
+constexpr int kMaxHidden = 8;
+constexpr int kMaxLayers = kMaxHidden + 1;
+constexpr int kMaxOutBlocks = (4 * kMaxOrb + 1 + 15) / 16;   // 17
+
+// Everything a kernel needs to know about one Hamiltonian + sector (passed by value).
+struct SysDev {
+  int n, na, nb, va, vb, W;
+  uint32_t nSa, nSb, nDaa, nDbb, nDab;     // block sizes of the canonical list
+  uint32_t npo_a, npv_a, npo_b, npv_b;     // pair counts C(m,2) of occ/vir per spin
+  uint32_t C;                              // list length incl. the diagonal
+  const double* h1e;                       // [n][n]
+  const double* S;                         // [i][j][a][b] = (ai|bj)
+  const double* J2;                        // [p][q] = (pp|qq)
+  const double* K2;                        // [p][q] = (pq|qp)
+  const double* J3;                        // [a][i][p] = (ai|pp)
+  const double* K3;                        // [a][i][p] = (ap|pi)
+  const uint16_t* pair_oa;                 // lexicographic pair k -> i | j << 8
+  const uint16_t* pair_va;
+  const uint16_t* pair_ob;
+  const uint16_t* pair_vb;
+};
+
+// Occupied / virtual spatial-orbital lists of one determinant (per wave, in LDS).
+struct SampleCtx {
+  uint64_t x[2];
+  uint8_t occ[2][kMaxOrb];
+  uint8_t vir[2][kMaxOrb];
+};
+
+// Ansatz geometry after packing (shared by the BF16 and FP64 kernels).
+//   layer l in [0, L]: l < L hidden (ReLU), l == L output (4n logits + phase row 4n).
+//   BF16: input K split in k-blocks of 32, outputs in o-blocks of 16; one packed
+//         fragment (ob, kb) = 64 lanes x 8 bf16 = 1 KiB.
+//   FP64: input K split in k-steps of 4; fragment (ob, ks) = 64 lanes x 1 double.
+struct MadeDev {
+  int n, L;
+  int nin[kMaxLayers];     // input width of layer l (true, unpadded)
+  int nout[kMaxLayers];    // output width of layer l (true; output layer 4n + 1)
+  int nk[kMaxLayers];      // k-blocks (BF16) or k-steps (FP64) of layer l
+  int nob[kMaxLayers];     // 16-wide output blocks of layer l
+  uint32_t woff[kMaxLayers];   // fragment offset of layer l in the packed buffer
+  uint32_t boff[kMaxLayers];   // bias offset of layer l (padded to 16 * nob)
+  uint32_t nfrag;              // total fragments
+  uint32_t nbias;              // total padded biases
+  const void* wfrag;           // packed weights (bf16x8 per lane or double per lane)
+  const void* bias;            // float (BF16 mode) or double (FP64 mode)
+};
+
+// ----------------------------------------------------------------------------- bit helpers
+template <int NW>
+__device__ __forceinline__ int parity_below(const uint64_t (&x)[NW], int k) {
+  int c = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int lo = 64 * w;
+    uint64_t m;
+    if (k >= lo + 64) m = ~0ull;
+    else if (k <= lo) m = 0ull;
+    else m = (1ull << (k - lo)) - 1ull;
+    c += __popcll(x[w] & m);
+  }
+  return c & 1;
+}
+
+template <int NW>
+__device__ __forceinline__ void flip(uint64_t (&x)[NW], int k) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+    if ((k >> 6) == w) x[w] ^= 1ull << (k & 63);
+}
+
+template <int NW>
+__device__ __forceinline__ int getbit(const uint64_t (&x)[NW], int k) {
+  int v = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+    if ((k >> 6) == w) v = (int)((x[w] >> (k & 63)) & 1ull);
+  return v;
+}
+
+// Spin-orbitals below 2p that are alpha (s=0) or beta (s=1): popcount of the prefix.
+template <int NW>
+__device__ __forceinline__ int count_spin_below(const uint64_t (&x)[NW], int p, int s) {
+  const uint64_t pat = s ? 0xAAAAAAAAAAAAAAAAull : 0x5555555555555555ull;
+  const int k = 2 * p;
+  int c = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int lo = 64 * w;
+    uint64_t m;
+    if (k >= lo + 64) m = ~0ull;
+    else if (k <= lo) m = 0ull;
+    else m = (1ull << (k - lo)) - 1ull;
+    c += __popcll(x[w] & m & pat);
+  }
+  return c;
+}
+
+// First spatial orbital where two determinants differ (n if equal).
+template <int NW>
+__device__ __forceinline__ int first_diff_orbital(const uint64_t (&a)[NW], const uint64_t (&b)[NW], int n) {
+  int k = 2 * n;
+#pragma unroll
+  for (int w = NW - 1; w >= 0; --w) {
+    const uint64_t d = a[w] ^ b[w];
+    if (d) k = 64 * w + __builtin_ctzll(d);
+  }
+  return k >> 1;
+}
+
+// ----------------------------------------------------------------------------- the generator
+// Kinds of list entries.
+enum : int { KIND_DIAG = 0, KIND_SINGLE = 1, KIND_DOUBLE_SAME = 2, KIND_DOUBLE_AB = 3 };
+
+struct Excitation {
+  int kind;
+  int spin;          // for singles and same-spin doubles
+  uint32_t sidx;     // index of a single inside all singles (alpha then beta)
+  int i, j, a, b;    // spatial orbitals (j, b unused for singles)
+  int I, J, A, Bq;   // spin-orbitals (-1 unused)
+};
+
+// Unrank entry t of the canonical list of the sample in `c` (see elocal.h).
+__device__ __forceinline__ Excitation unrank(const SysDev& S, const SampleCtx& c, uint32_t t) {
+  Excitation e;
+  e.kind = KIND_DIAG; e.spin = 0; e.sidx = 0;
+  e.i = e.j = e.a = e.b = -1;
+  e.I = e.J = e.A = e.Bq = -1;
+  if (t == 0) return e;
+  uint32_t u = t - 1;
+  if (u < S.nSa) {
+    e.kind = KIND_SINGLE; e.spin = 0; e.sidx = u;
+    e.i = c.occ[0][u / (uint32_t)S.va]; e.a = c.vir[0][u % (uint32_t)S.va];
+  } else if ((u -= S.nSa) < S.nSb) {
+    e.kind = KIND_SINGLE; e.spin = 1; e.sidx = S.nSa + u;
+    e.i = c.occ[1][u / (uint32_t)S.vb]; e.a = c.vir[1][u % (uint32_t)S.vb];
+  } else if ((u -= S.nSb) < S.nDaa) {
+    e.kind = KIND_DOUBLE_SAME; e.spin = 0;
+    const uint32_t po = u / S.npv_a, pv = u % S.npv_a;
+    const uint16_t oo = S.pair_oa[po], vv = S.pair_va[pv];
+    e.i = c.occ[0][oo & 0xFF]; e.j = c.occ[0][oo >> 8];
+    e.a = c.vir[0][vv & 0xFF]; e.b = c.vir[0][vv >> 8];
+  } else if ((u -= S.nDaa) < S.nDbb) {
+    e.kind = KIND_DOUBLE_SAME; e.spin = 1;
+    const uint32_t po = u / S.npv_b, pv = u % S.npv_b;
+    const uint16_t oo = S.pair_ob[po], vv = S.pair_vb[pv];
+    e.i = c.occ[1][oo & 0xFF]; e.j = c.occ[1][oo >> 8];
+    e.a = c.vir[1][vv & 0xFF]; e.b = c.vir[1][vv >> 8];
+  } else {
+    u -= S.nDbb;
+    e.kind = KIND_DOUBLE_AB;
+    const uint32_t nbvb = S.nSb;
+    const uint32_t u1 = u / nbvb, u2 = u % nbvb;
+    e.i = c.occ[0][u1 / (uint32_t)S.va]; e.a = c.vir[0][u1 % (uint32_t)S.va];
+    e.j = c.occ[1][u2 / (uint32_t)S.vb]; e.b = c.vir[1][u2 % (uint32_t)S.vb];
+  }
+  if (e.kind == KIND_SINGLE) {
+    e.I = 2 * e.i + e.spin; e.A = 2 * e.a + e.spin;
+  } else if (e.kind == KIND_DOUBLE_SAME) {
+    e.I = 2 * e.i + e.spin; e.J = 2 * e.j + e.spin; e.A = 2 * e.a + e.spin; e.Bq = 2 * e.b + e.spin;
+  } else if (e.kind == KIND_DOUBLE_AB) {
+    e.I = 2 * e.i; e.J = 2 * e.j + 1; e.A = 2 * e.a; e.Bq = 2 * e.b + 1;
+  }
+  return e;
+}
+
+// x' = a+_A a+_B a_J a_I x and the sign, operator by operator (JW parity of the prefix).
+template <int NW>
+__device__ __forceinline__ int apply_excitation(const uint64_t (&x)[NW], const Excitation& e,
+                                                uint64_t (&xp)[NW]) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) xp[w] = x[w];
+  if (e.kind == KIND_DIAG) return 1;
+  int par = parity_below<NW>(xp, e.I);
+  flip<NW>(xp, e.I);
+  if (e.J >= 0) { par ^= parity_below<NW>(xp, e.J); flip<NW>(xp, e.J); }
+  if (e.Bq >= 0) { par ^= parity_below<NW>(xp, e.Bq); flip<NW>(xp, e.Bq); }
+  par ^= parity_below<NW>(xp, e.A);
+  flip<NW>(xp, e.A);
+  return par ? -1 : 1;
+}
+
+// Slater--Condon value (before the sign). Fs: this sample's single values; ed: its diagonal.
+__device__ __forceinline__ double excitation_value(const SysDev& S, const Excitation& e,
+                                                   const double* Fs, double ed) {
+  const int n = S.n;
+  switch (e.kind) {
+    case KIND_DIAG: return ed;
+    case KIND_SINGLE: return Fs[e.sidx];
+    case KIND_DOUBLE_SAME: {
+      const size_t ab = (size_t)e.a * n + e.b;
+      const double d = S.S[((size_t)e.i * n + e.j) * n * n + ab];
+      const double x = S.S[((size_t)e.j * n + e.i) * n * n + ab];
+      return d - x;
+    }
+    default:
+      return S.S[(((size_t)e.i * n + e.j) * n + e.a) * n + e.b];
+  }
+}
+
+// Build the occupied/virtual lists of x in `c` (one wave; lane p handles orbital p).
+template <int NW>
+__device__ __forceinline__ void build_ctx(const SysDev& S, const uint64_t (&x)[NW], SampleCtx& c,
+                                          int lane) {
+  const int p = lane;
+  const bool in = p < S.n;
+  const bool oa = in && getbit<NW>(x, 2 * p);
+  const bool ob = in && getbit<NW>(x, 2 * p + 1);
+  const uint64_t ma = __ballot(oa);
+  const uint64_t mb = __ballot(ob);
+  const uint64_t below = (p == 0) ? 0ull : ((p >= 64) ? ~0ull : ((1ull << p) - 1ull));
+  if (in) {
+    const int ia = __popcll(ma & below), ib = __popcll(mb & below);
+    if (oa) c.occ[0][ia] = (uint8_t)p; else c.vir[0][p - ia] = (uint8_t)p;
+    if (ob) c.occ[1][ib] = (uint8_t)p; else c.vir[1][p - ib] = (uint8_t)p;
+  }
+  if (lane < NW) c.x[lane] = x[lane];
+}
+
+}  // namespace elocal

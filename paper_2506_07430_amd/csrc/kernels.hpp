@@ -1,0 +1,101 @@
+// Launch interfaces of the HIP kernels (host side of libelocal).
+#pragma once
+#include "elocal_internal.hpp"
+
+namespace elocal {
+
+// Offsets of the pieces of the caller's flat parameter vector.
+struct ThetaLayout {
+  uint32_t offW[kMaxLayers];
+  uint32_t offb[kMaxLayers];
+  uint32_t offwphi, offbphi, P;
+};
+
+// Arguments of the fused local-energy kernels.
+struct EvalArgs {
+  SysDev sys;
+  MadeDev made;
+  const uint64_t* x;
+  int64_t B;
+  const double* ediag;     // [B]
+  const double* F;         // [B][nSa + nSb]
+  const float* lpx;        // [B][n]   BF16 mode: log p_p(s_p) of each sample
+  const double* lpx64;     // [B][n]   FP64 mode
+  const double* zphi;      // [B]      phase logit of each sample
+  double* partial;         // [n_items][2]
+  int64_t n_items;
+  uint32_t ips;            // work items per sample
+  uint32_t tpi;            // row tiles per work item
+  uint32_t lds_bias_off;   // byte offset of the biases in LDS (weights at 0)
+  uint32_t lds_ctx_off;    // byte offset of the per-wave contexts
+};
+
+// Arguments of the ansatz pass over the samples themselves.
+struct RowsArgs {
+  SysDev sys;
+  MadeDev made;
+  const uint64_t* x;
+  int64_t B;
+  float* lpx;              // [B][n] (BF16 mode)
+  double* lpx64;           // [B][n] (FP64 mode)
+  double* zphi;            // [B]
+  double* logpsi;          // [B][2] or null
+};
+
+hipError_t launch_build_tables(int n, const double* eri, double* S, double* J2, double* K2,
+                               double* J3, double* K3, hipStream_t st);
+hipError_t launch_prep(const SysDev& S, const uint64_t* x, int64_t B, double* ediag, double* F,
+                       hipStream_t st);
+hipError_t launch_connect(const SysDev& S, const uint64_t* x, int64_t B, const double* ediag,
+                          const double* F, uint64_t* xp, double* hval, int8_t* sign, uint32_t* exc,
+                          hipStream_t st);
+hipError_t launch_check(const SysDev& S, const uint64_t* x, int64_t B, unsigned long long* bad,
+                        hipStream_t st);
+
+// Ansatz (precision-specific): pack caller parameters, run the sample pass, run the
+// fused evaluation; `hmax` is the padded hidden width class (32, 64, 128, 256).
+hipError_t launch_pack_bf16(const MadeDev& M, const ThetaLayout& T, const uint16_t* theta,
+                            void* frag, float* bias, hipStream_t st);
+hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, hipStream_t st);
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, bool lds_weights, size_t lds_bytes,
+                            unsigned grid, hipStream_t st);
+
+hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta,
+                           void* frag, double* bias, hipStream_t st);
+hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st);
+hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream_t st);
+
+// Sum of the per-item partials plus the diagonal: eloc[b] = ediag[b] + sum_s partial[b][s].
+hipError_t launch_reduce(const double* ediag, const double* partial, int64_t B, uint32_t ips,
+                         double* eloc, hipStream_t st);
+
+// Statistics and gradient (FP64).
+hipError_t launch_stats(const double* eloc, const double* w, int64_t B, double* stats, hipStream_t st);
+
+struct GradPlan {
+  int n, na, nb, L;
+  int dims[kMaxLayers + 1];    // 2n, widths..., 4n + 1 (phase row appended)
+  ThetaLayout T;
+  int precision;
+  const void* theta;
+  const uint64_t* x;
+  const double* w;
+  const double* eloc;
+  int64_t B;
+  double* stats;
+  double* dtheta;
+  // workspace pieces
+  double* Wm[kMaxLayers];      // masked weights [out][in] (output layer with phase row)
+  double* bm[kMaxLayers];      // biases [out]
+  double* h[kMaxLayers + 1];   // activations: h[0] = bits [B][2n], h[l] [B][dims[l]], h[L+1] logits
+  double* d0;                  // [B][maxdim] backward buffers
+  double* d1;
+  double* part;                // split-K partials
+  double* ones;                // [B]
+  double* dW[kMaxLayers];      // [out][in]
+  double* db[kMaxLayers];      // [out]
+  int splits;
+};
+hipError_t launch_grad(const GradPlan& G, hipStream_t st);
+
+}  // namespace elocal

@@ -1,0 +1,321 @@
+// Autoregressive ansatz on FP64 matrix cores (v_mfma_f64_16x16x4f64) and the fused
+// all-FP64 local-energy kernel.
+//
+// Same transposed formulation as the BF16 path (weights = A operand, 16 rows = B
+// operand). The FP64 instruction returns row 4*i + lane/16 of the 16x16 block in
+// register i, so the packer stores weight row 16*ob + 4*(rho%4) + rho/4 at A-row rho;
+// lane group g then holds units 16*ob + 4g + i in register i, exactly as in the BF16
+// path, and register i of block ob is the B operand of k-step 4*ob + i of the next
+// layer. Output orbital 4*ob + g again lands in one lane.
+#include "elocal_internal.hpp"
+#include "kernels.hpp"
+
+namespace elocal {
+
+__device__ __forceinline__ bool made_allowed64(int n, int L, int l, int o, int k) {
+  const int nm1 = n - 1;
+  if (l == 0) return (o % nm1) + 1 >= k / 2 + 1;
+  if (l < L) return (o % nm1) + 1 >= (k % nm1) + 1;
+  if (o == 4 * n) return true;
+  return (o / 4) + 1 > (k % nm1) + 1;
+}
+
+__global__ void k_pack_f64(MadeDev M, ThetaLayout T, const double* __restrict__ theta,
+                           double* __restrict__ frag, double* __restrict__ bias) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < M.nfrag * 64u) {
+    const uint32_t f = gid >> 6;
+    const int lane = gid & 63;
+    int l = 0;
+    while (l < M.L && f >= M.woff[l + 1]) ++l;
+    const uint32_t local = f - M.woff[l];
+    const int ob = local / M.nk[l], ks = local % M.nk[l];
+    const int rho = lane & 15, g = lane >> 4;
+    const int o = 16 * ob + 4 * (rho & 3) + (rho >> 2);
+    const int k = (l == 0) ? 4 * ks + g : 16 * (ks >> 2) + 4 * g + (ks & 3);
+    double v = 0.0;
+    if (o < M.nout[l] && k < M.nin[l] && made_allowed64(M.n, M.L, l, o, k)) {
+      if (l == M.L && o == 4 * M.n) v = theta[T.offwphi + k];
+      else v = theta[T.offW[l] + (uint32_t)o * M.nin[l] + k];
+    }
+    frag[gid] = v;
+  }
+  if (gid < M.nbias) {
+    int l = 0;
+    while (l < M.L && gid >= M.boff[l + 1]) ++l;
+    const int o = gid - M.boff[l];
+    double v = 0.0;
+    if (o < M.nout[l]) v = (l == M.L && o == 4 * M.n) ? theta[T.offbphi] : theta[T.offb[l] + o];
+    bias[gid] = v;
+  }
+}
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, const f64x4& c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f64x4 load_bias4_64(const double* bias, uint32_t off) {
+  f64x4 r;
+  r[0] = bias[off]; r[1] = bias[off + 1]; r[2] = bias[off + 2]; r[3] = bias[off + 3];
+  return r;
+}
+
+__device__ __forceinline__ f64x4 relu4(const f64x4& a) {
+  f64x4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = a[i] > 0.0 ? a[i] : 0.0;
+  return r;
+}
+
+// Network on one 16-row block (row r of lane r); epi(ob, acc) per output block.
+template <int HMAX, int NW, class Epi>
+__device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ W,
+                                        const double* __restrict__ bias, const uint64_t (&xr)[NW],
+                                        int lane, Epi&& epi) {
+  constexpr int OB = HMAX / 16;
+  constexpr int KS = HMAX / 4;
+  const int g = lane >> 4;
+  f64x4 cur[OB];
+  {
+    const int nk = M.nk[0], nob = M.nob[0];
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      if (ob < nob) {
+        f64x4 acc = load_bias4_64(bias, M.boff[0] + 16 * ob + 4 * g);
+        const double* wp = W + (size_t)(M.woff[0] + ob * nk) * 64 + lane;
+        for (int ks = 0; ks < nk; ++ks) {
+          const double bv = (double)getbit<NW>(xr, 4 * ks + g);
+          acc = mfma_f64(wp[ks * 64], bv, acc);
+        }
+        cur[ob] = relu4(acc);
+      }
+    }
+  }
+  for (int l = 1; l < M.L; ++l) {
+    const int nk = M.nk[l], nob = M.nob[l];
+    f64x4 nxt[OB];
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      if (ob < nob) {
+        f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
+        const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          if (ks < nk) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
+        nxt[ob] = relu4(acc);
+      }
+    }
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) cur[ob] = nxt[ob];
+  }
+  {
+    const int l = M.L, nk = M.nk[l], nob = M.nob[l];
+#pragma unroll 1
+    for (int ob = 0; ob < nob; ++ob) {
+      f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
+      const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        if (ks < nk) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
+      epi(ob, acc);
+    }
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ double cond_logp64(const uint64_t (&x)[NW], int p, int n, int na, int nb,
+                                              const f64x4& z) {
+  const int cu = count_spin_below<NW>(x, p, 0), cd = count_spin_below<NW>(x, p, 1);
+  const int left = n - p - 1;
+  const int s = getbit<NW>(x, 2 * p) + 2 * getbit<NW>(x, 2 * p + 1);
+  bool ok[4];
+  double m = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = cu + (q & 1), d = cd + (q >> 1);
+    ok[q] = (u <= na) && (d <= nb) && (u + left >= na) && (d + left >= nb);
+    if (ok[q]) m = fmax(m, z[q]);
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (ok[q]) sum += exp(z[q] - m);
+  const double zs = (s == 0) ? z[0] : (s == 1) ? z[1] : (s == 2) ? z[2] : z[3];
+  return zs - m - log(sum);
+}
+
+__device__ __forceinline__ void wave_sync_lds64() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int HMAX, int NW>
+__global__ void __launch_bounds__(256) k_rows_f64(RowsArgs P) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t b0 = wave * 16;
+  if (b0 >= P.B) return;
+  const MadeDev& M = P.made;
+  const int n = P.sys.n, na = P.sys.na, nb = P.sys.nb;
+  const int64_t rb = b0 + r16;
+  const int64_t bb = rb < P.B ? rb : b0;
+  uint64_t xr[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) xr[w] = P.x[bb * NW + w];
+  const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
+  double A = 0.0, zp = 0.0;
+  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.bias, xr, lane,
+                    [&](int ob, const f64x4& a) {
+                      const int p = 4 * ob + g;
+                      if (p < n) {
+                        const double lp = cond_logp64<NW>(xr, p, n, na, nb, a);
+                        A += lp;
+                        if (rb < P.B) P.lpx64[rb * n + p] = lp;
+                      }
+                      if (ob == ob_phi && g == g_phi) zp = a[0];
+                    });
+  A += __shfl_xor(A, 16);
+  A += __shfl_xor(A, 32);
+  zp = __shfl(zp, g_phi * 16 + r16);
+  if (g == 0 && rb < P.B) {
+    P.zphi[rb] = zp;
+    if (P.logpsi) {
+      P.logpsi[2 * rb] = 0.5 * A;
+      P.logpsi[2 * rb + 1] = 2.0 * M_PI / (1.0 + exp(-zp));
+    }
+  }
+}
+
+struct WaveCtx64 {
+  SampleCtx c;
+  double lpx[kMaxOrb];
+};
+
+template <int HMAX, int NW>
+__global__ void __launch_bounds__(256) k_eval_f64(EvalArgs P) {
+  __shared__ WaveCtx64 ctxs[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+  const MadeDev& M = P.made;
+  const SysDev& S = P.sys;
+  const double* W = (const double*)M.wfrag;
+  const double* bias = (const double*)M.bias;
+  WaveCtx64& wc = ctxs[wid];
+  const int n = S.n, na = S.na, nb = S.nb;
+  const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
+  const uint32_t nS = S.nSa + S.nSb;
+  int64_t cur_b = -1;
+  uint64_t xs[NW];
+  double sig_x = 0.0, ed = 0.0;
+  const double* Fs = P.F;
+  for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < P.n_items; item += (int64_t)gridDim.x * 4) {
+    const int64_t b = item / P.ips;
+    const uint32_t seg = (uint32_t)(item % P.ips);
+    if (b != cur_b) {
+      wave_sync_lds64();
+#pragma unroll
+      for (int w = 0; w < NW; ++w) xs[w] = P.x[b * NW + w];
+      build_ctx<NW>(S, xs, wc.c, lane);
+      if (lane < n) wc.lpx[lane] = P.lpx64[b * n + lane];
+      wave_sync_lds64();
+      sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
+      ed = P.ediag[b];
+      Fs = P.F + (size_t)b * nS;
+      cur_b = b;
+    }
+    double acc_re = 0.0, acc_im = 0.0;
+    for (uint32_t tile = 0; tile < P.tpi; ++tile) {
+      const uint32_t t0 = 1u + (seg * P.tpi + tile) * 16u;
+      if (t0 >= S.C) break;
+      const uint32_t t = t0 + r16;
+      uint64_t xp[NW];
+      double hv = 0.0;
+      if (t < S.C) {
+        const Excitation e = unrank(S, wc.c, t);
+        const int sg = apply_excitation<NW>(xs, e, xp);
+        if (g == 0) {
+          const double v = excitation_value(S, e, Fs, ed);
+          hv = sg < 0 ? -v : v;
+        }
+      } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xp[w] = xs[w];
+      }
+      const int p0 = first_diff_orbital<NW>(xs, xp, n);
+      double dA = 0.0, zp = 0.0;
+      mlp_f64<HMAX, NW>(M, W, bias, xp, lane, [&](int ob, const f64x4& a) {
+        const int p = 4 * ob + g;
+        if (p < n && p >= p0) dA += cond_logp64<NW>(xp, p, n, na, nb, a) - wc.lpx[p];
+        if (ob == ob_phi && g == g_phi) zp = a[0];
+      });
+      dA += __shfl_xor(dA, 16);
+      dA += __shfl_xor(dA, 32);
+      zp = __shfl(zp, g_phi * 16 + r16);
+      if (g == 0) {
+        const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-zp)) - sig_x);
+        double sn, cs;
+        sincos(dphi, &sn, &cs);
+        const double mag = hv * exp(0.5 * dA);
+        acc_re += mag * cs;
+        acc_im += mag * sn;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      acc_re += __shfl_xor(acc_re, off);
+      acc_im += __shfl_xor(acc_im, off);
+    }
+    if (lane == 0) {
+      P.partial[2 * item] = acc_re;
+      P.partial[2 * item + 1] = acc_im;
+    }
+  }
+}
+
+hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta, void* frag,
+                           double* bias, hipStream_t st) {
+  const uint32_t total = M.nfrag * 64u > M.nbias ? M.nfrag * 64u : M.nbias;
+  hipLaunchKernelGGL(k_pack_f64, dim3((total + 255) / 256), dim3(256), 0, st, M, T, theta,
+                     (double*)frag, bias);
+  return hipGetLastError();
+}
+
+template <int HMAX>
+static hipError_t rows_f64_h(const RowsArgs& A, hipStream_t st) {
+  const int64_t waves = (A.B + 15) / 16;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  if (A.sys.W == 1) hipLaunchKernelGGL((k_rows_f64<HMAX, 1>), dim3(blocks), dim3(256), 0, st, A);
+  else hipLaunchKernelGGL((k_rows_f64<HMAX, 2>), dim3(blocks), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st) {
+  if (A.B <= 0) return hipSuccess;
+  switch (hmax) {
+    case 32: return rows_f64_h<32>(A, st);
+    case 64: return rows_f64_h<64>(A, st);
+    case 128: return rows_f64_h<128>(A, st);
+    case 256: return rows_f64_h<256>(A, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int HMAX>
+static hipError_t eval_f64_h(const EvalArgs& A, unsigned grid, hipStream_t st) {
+  if (A.sys.W == 1) hipLaunchKernelGGL((k_eval_f64<HMAX, 1>), dim3(grid), dim3(256), 0, st, A);
+  else hipLaunchKernelGGL((k_eval_f64<HMAX, 2>), dim3(grid), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream_t st) {
+  if (A.n_items <= 0) return hipSuccess;
+  switch (hmax) {
+    case 32: return eval_f64_h<32>(A, grid, st);
+    case 64: return eval_f64_h<64>(A, grid, st);
+    case 128: return eval_f64_h<128>(A, grid, st);
+    case 256: return eval_f64_h<256>(A, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace elocal

@@ -1,0 +1,265 @@
+"""Python binding of libelocal (ctypes; argument marshalling only).
+
+Every computation happens in the HIP library. PyTorch supplies device memory and
+the current stream. Bitstrings are int64 tensors holding the uint64 words
+(bit k of word k // 64 is spin-orbital k = 2p + s). If the library is not built or
+cannot be loaded, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libelocal.so")
+
+FP64 = 0
+BF16 = 1
+OP_CONNECT, OP_EVAL, OP_GRAD = 0, 1, 2
+
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_CONFIG", 3: "E_WORKSPACE", 4: "E_NOMEM", 5: "E_DEVICE",
+          6: "E_UNSUPPORTED"}
+
+
+class ElocalError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"elocal {STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Ansatz(ctypes.Structure):
+    _fields_ = [("n_hidden", ctypes.c_int), ("widths", ctypes.POINTER(ctypes.c_int)),
+                ("precision", ctypes.c_int), ("theta", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ElocalError(5, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.elocal_create.argtypes = [vp, vp, i32, i32, i32, P(vp)]
+        L.elocal_destroy.argtypes = [vp]
+        L.elocal_num_connected.argtypes = [vp]
+        L.elocal_num_connected.restype = i64
+        L.elocal_words.argtypes = [vp]
+        L.elocal_num_params.argtypes = [i32, i32, P(ctypes.c_int)]
+        L.elocal_num_params.restype = i64
+        L.elocal_workspace_bytes.argtypes = [vp, P(_Ansatz), i64, i32]
+        L.elocal_workspace_bytes.restype = sz
+        L.elocal_connect.argtypes = [vp, vp, vp, i64, vp, sz, vp, vp, vp, vp]
+        L.elocal_eval.argtypes = [vp, vp, P(_Ansatz), vp, i64, vp, sz, vp, vp]
+        L.elocal_stats.argtypes = [vp, vp, vp, i64, vp]
+        L.elocal_grad.argtypes = [vp, vp, P(_Ansatz), vp, vp, vp, i64, vp, sz, vp, vp]
+        L.elocal_check_samples.argtypes = [vp, vp, vp, i64, vp, sz, P(i64)]
+        L.elocal_last_error.restype = ctypes.c_char_p
+        L.elocal_timing_enable.argtypes = [vp, i32]
+        L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
+        for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
+                  "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return ["elocal_create", "elocal_destroy", "elocal_num_connected", "elocal_words", "elocal_num_params",
+            "elocal_workspace_bytes", "elocal_connect", "elocal_eval", "elocal_stats", "elocal_grad",
+            "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_last_error"]
+
+
+def _check(status: int):
+    if status != 0:
+        raise ElocalError(status, lib().elocal_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def num_params(n_orb: int, widths: Sequence[int]) -> int:
+    w = (ctypes.c_int * len(widths))(*widths)
+    p = lib().elocal_num_params(n_orb, len(widths), w)
+    if p < 0:
+        raise ElocalError(1, f"unsupported ansatz shape n={n_orb} widths={list(widths)}")
+    return int(p)
+
+
+class Ansatz:
+    """Hidden widths + precision + a flat parameter tensor on the GPU."""
+
+    def __init__(self, widths: Sequence[int], theta: torch.Tensor, precision: int):
+        self.widths = tuple(int(w) for w in widths)
+        self.precision = int(precision)
+        want = torch.float64 if precision == FP64 else torch.bfloat16
+        if theta.dtype != want or not theta.is_cuda or not theta.is_contiguous():
+            raise ElocalError(1, f"theta must be a contiguous CUDA {want} tensor")
+        self.theta = theta
+        self._w = (ctypes.c_int * len(self.widths))(*self.widths)
+        self._s = _Ansatz(len(self.widths), self._w, self.precision, ctypes.c_void_p(theta.data_ptr()))
+
+    def ref(self):
+        self._s.theta = ctypes.c_void_p(self.theta.data_ptr())
+        return ctypes.byref(self._s)
+
+
+class Hamiltonian:
+    """A device-resident Hamiltonian for one (n_orb, n_alpha, n_beta) sector."""
+
+    def __init__(self, h1e, eri, n_orb: int, n_alpha: int, n_beta: int):
+        h1e = np.ascontiguousarray(np.asarray(h1e, dtype=np.float64))
+        eri = np.ascontiguousarray(np.asarray(eri, dtype=np.float64))
+        if h1e.size != n_orb * n_orb or eri.size != n_orb ** 4:
+            raise ElocalError(1, "integral arrays do not match n_orb")
+        self.n, self.na, self.nb = n_orb, n_alpha, n_beta
+        h = ctypes.c_void_p()
+        _check(lib().elocal_create(h1e.ctypes.data, eri.ctypes.data, n_orb, n_alpha, n_beta, ctypes.byref(h)))
+        self._h = h
+        self.C = int(lib().elocal_num_connected(h))
+        self.W = int(lib().elocal_words(h))
+        self._ws = {}
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().elocal_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ workspace
+    def workspace_bytes(self, op: int, B: int, ansatz: Optional[Ansatz] = None) -> int:
+        ref = ansatz.ref() if ansatz is not None else None
+        n = lib().elocal_workspace_bytes(self._h, ref, int(B), op)
+        if n == 0:
+            raise ElocalError(1, lib().elocal_last_error().decode())
+        return int(n)
+
+    def _workspace(self, op: int, B: int, ansatz: Optional[Ansatz] = None) -> Tuple[torch.Tensor, int]:
+        need = self.workspace_bytes(op, B, ansatz)
+        buf = self._ws.get(op)
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[op] = buf
+        return buf, buf.numel()
+
+    def _x(self, x: torch.Tensor) -> torch.Tensor:
+        if x.dtype != torch.int64 or not x.is_cuda or x.dim() != 2 or x.shape[1] != self.W:
+            raise ElocalError(1, f"x must be a CUDA int64 tensor [B, {self.W}]")
+        return x.contiguous()
+
+    # ------------------------------------------------------------------ calls
+    def connect(self, x: torch.Tensor, stream=None):
+        x = self._x(x)
+        B = x.shape[0]
+        xp = torch.empty((B, self.C, self.W), dtype=torch.int64, device=x.device)
+        hv = torch.empty((B, self.C), dtype=torch.float64, device=x.device)
+        sg = torch.empty((B, self.C), dtype=torch.int8, device=x.device)
+        ex = torch.empty((B, self.C), dtype=torch.int32, device=x.device)
+        ws, nb = self._workspace(OP_CONNECT, B)
+        _check(lib().elocal_connect(self._h, _stream(stream), x.data_ptr(), B, ws.data_ptr(), nb,
+                                    xp.data_ptr(), hv.data_ptr(), sg.data_ptr(), ex.data_ptr()))
+        return xp, hv, sg, ex
+
+    def eval(self, ansatz: Ansatz, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+             logpsi: Optional[torch.Tensor] = None, want_logpsi: bool = True, stream=None):
+        """(eloc [B, 2] float64 (re, im), logpsi [B, 2] (A, phi) or None)."""
+        x = self._x(x)
+        B = x.shape[0]
+        eloc = out if out is not None else torch.empty((B, 2), dtype=torch.float64, device=x.device)
+        if want_logpsi and logpsi is None:
+            logpsi = torch.empty((B, 2), dtype=torch.float64, device=x.device)
+        ws, nb = self._workspace(OP_EVAL, B, ansatz)
+        _check(lib().elocal_eval(self._h, _stream(stream), ansatz.ref(), x.data_ptr(), B, ws.data_ptr(), nb,
+                                 eloc.data_ptr(), _ptr(logpsi) if want_logpsi else None))
+        return eloc, logpsi
+
+    def grad(self, ansatz: Ansatz, x: torch.Tensor, w: torch.Tensor, eloc: torch.Tensor,
+             stats: Optional[torch.Tensor] = None, dtheta: Optional[torch.Tensor] = None, stream=None):
+        """(stats [4] = (Re<E>, Im<E>, var, sum w), dtheta [P] float64)."""
+        x = self._x(x)
+        B = x.shape[0]
+        w = w.to(torch.float64).contiguous()
+        eloc = eloc.contiguous()
+        if stats is None:
+            stats = torch.empty(4, dtype=torch.float64, device=x.device)
+        if dtheta is None:
+            dtheta = torch.empty(ansatz.theta.numel(), dtype=torch.float64, device=x.device)
+        ws, nb = self._workspace(OP_GRAD, B, ansatz)
+        _check(lib().elocal_grad(self._h, _stream(stream), ansatz.ref(), x.data_ptr(), w.data_ptr(),
+                                 eloc.data_ptr(), B, ws.data_ptr(), nb, stats.data_ptr(), dtheta.data_ptr()))
+        return stats, dtheta
+
+    def timing(self, on: bool = True):
+        """Record HIP events around the fused local-energy kernel of every eval."""
+        _check(lib().elocal_timing_enable(self._h, int(on)))
+
+    def kernel_time(self, reset: bool = True):
+        """(summed milliseconds, launches) of the fused kernel since the last reset."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib().elocal_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        return ms.value, int(n.value)
+
+    def check_samples(self, x: torch.Tensor, stream=None) -> int:
+        x = self._x(x)
+        ws = torch.empty(8, dtype=torch.uint8, device=x.device)
+        bad = ctypes.c_int64(0)
+        st = lib().elocal_check_samples(self._h, _stream(stream), x.data_ptr(), x.shape[0], ws.data_ptr(), 8,
+                                        ctypes.byref(bad))
+        if st not in (0, 2):
+            _check(st)
+        return int(bad.value)
+
+
+def stats(eloc: torch.Tensor, w: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty(4, dtype=torch.float64, device=eloc.device)
+    w = w.to(torch.float64).contiguous()
+    _check(lib().elocal_stats(_stream(stream), eloc.contiguous().data_ptr(), w.data_ptr(), eloc.shape[0],
+                              out.data_ptr()))
+    return out
+
+
+class ElocEnergy(torch.autograd.Function):
+    """Forward: Re<E> over the batch (local energies from the HIP library).
+
+    Backward: grad_output times the VMC gradient 2 Re <(E_loc - <E>) d log Psi*> --
+    the variational-energy gradient estimator, not the derivative of the
+    fixed-sample mean (the samples themselves depend on theta).
+    """
+
+    @staticmethod
+    def forward(ctx, theta, ham: Hamiltonian, widths, precision, x, w):
+        ans = Ansatz(widths, theta.detach().contiguous(), precision)
+        eloc, _ = ham.eval(ans, x, want_logpsi=False)
+        st = stats(eloc, w)
+        ctx.ham, ctx.ans = ham, ans
+        ctx.save_for_backward(x, w, eloc)
+        ctx.stats = st
+        return st[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        x, w, eloc = ctx.saved_tensors
+        _, dtheta = ctx.ham.grad(ctx.ans, x, w, eloc)
+        return (g * dtheta).to(ctx.ans.theta.dtype), None, None, None, None, None

@@ -161,7 +161,7 @@ def sort_unique_words(x: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.uint64)
     key = x[:, ::-1]                      # most significant word first
     u = np.unique(key, axis=0)
-    return np.ascontiguousarray(u[:, ::-1])
+    return u[:, ::-1].copy()
 
 
 def uniform_determinants(sys: System, count: int, g: np.random.Generator) -> np.ndarray:
