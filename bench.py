@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of this many MiB (a known-size reference "
+                         "for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
@@ -92,6 +95,15 @@ def main():
     eloc = torch.empty((B, 2), dtype=torch.float64, device=dev)
     stats = torch.empty(4, dtype=torch.float64, device=dev)
     dth = torch.empty(th64.numel(), dtype=torch.float64, device=dev)
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(ans):
         ham.eval(ans, x, out=eloc, want_logpsi=False)

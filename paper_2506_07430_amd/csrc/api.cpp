@@ -126,6 +126,32 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   }
   M.nfrag = wo;
   M.nbias = bo;
+  // k-block ranges of the degree-sorted BF16 packing (FP64 packing is unsorted: full range)
+  for (int l = 0; l <= L; ++l)
+    for (int ob = 0; ob < kMaxOutBlocks; ++ob) M.kend[l][ob] = (uint8_t)M.nk[l];
+  if (a->precision == ELOCAL_BF16) {
+    auto deg_at = [&](int width, int u) { return sorted_unit(n, width, u) % (n - 1) + 1; };
+    auto count_le = [&](int width, int D) {
+      int c = 0;
+      for (int j = 0; j < width; ++j) c += (j % (n - 1)) + 1 <= D;
+      return c;
+    };
+    for (int l = 0; l <= L; ++l) {
+      for (int ob = 0; ob < M.nob[l]; ++ob) {
+        int need;   // input units (or bits) this block can see
+        if (l < L) {
+          const int w = a->widths[l];
+          const int mmax = deg_at(w, std::min(16 * ob + 15, w - 1));
+          need = (l == 0) ? 2 * mmax : count_le(a->widths[l - 1], mmax);
+        } else {
+          const bool phase = 16 * ob <= 4 * n && 4 * n < 16 * ob + 16;
+          const int D = std::min(4 * ob + 3, n - 1);
+          need = phase ? M.nin[l] : count_le(a->widths[L - 1], D);
+        }
+        M.kend[l][ob] = (uint8_t)std::min(M.nk[l], (need + 31) / 32);
+      }
+    }
+  }
   G.wbytes = (size_t)wo * 64 * (a->precision == ELOCAL_BF16 ? 16 : 8);
   G.bbytes = (size_t)bo * (a->precision == ELOCAL_BF16 ? 4 : 8);
   // caller's flat layout
@@ -156,8 +182,9 @@ struct EvalPlan {
 
 EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
   EvalPlan p{};
-  p.rows_per_tile = (G.precision == ELOCAL_BF16) ? 32 : 16;
-  p.tpi = 16;
+  // BF16: groups of 64 entries (one per lane), 8 per item; FP64: tiles of 16, 16 per item
+  p.rows_per_tile = (G.precision == ELOCAL_BF16) ? 64 : 16;
+  p.tpi = (G.precision == ELOCAL_BF16) ? 8 : 16;
   const uint64_t rows = h->sys.C - 1;   // the diagonal entry needs no ansatz call
   const uint64_t per_item = (uint64_t)p.rows_per_tile * p.tpi;
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
@@ -270,6 +297,11 @@ SysDev build_sys(int n, int na, int nb) {
   s.nDbb = s.npo_b * s.npv_b;
   s.nDab = s.nSa * s.nSb;
   s.C = 1u + s.nSa + s.nSb + s.nDaa + s.nDbb + s.nDab;
+  s.f_va = make_fastdiv((uint32_t)s.va);
+  s.f_vb = make_fastdiv((uint32_t)s.vb);
+  s.f_npv_a = make_fastdiv(s.npv_a);
+  s.f_npv_b = make_fastdiv(s.npv_b);
+  s.f_nSb = make_fastdiv(s.nSb);
   return s;
 }
 

@@ -14,12 +14,31 @@ constexpr int kMaxHidden = 8;
 constexpr int kMaxLayers = kMaxHidden + 1;
 constexpr int kMaxOutBlocks = (4 * kMaxOrb + 1 + 15) / 16;   // 17
 
+// Division by a fixed divisor d as a multiply and shift: q = (u * m) >> 40 with
+// m = ceil(2^40 / d) is exact whenever u * d < 2^40 (here u < 2^21, d < 2^13).
+struct FastDiv {
+  uint32_t d;
+  uint64_t m;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.m = d ? ((1ull << 40) + d - 1) / d : 0ull;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t u, const FastDiv& f) {
+  return (uint32_t)(((uint64_t)u * f.m) >> 40);
+}
+
 // Everything a kernel needs to know about one Hamiltonian + sector (passed by value).
 struct SysDev {
   int n, na, nb, va, vb, W;
   uint32_t nSa, nSb, nDaa, nDbb, nDab;     // block sizes of the canonical list
   uint32_t npo_a, npv_a, npo_b, npv_b;     // pair counts C(m,2) of occ/vir per spin
   uint32_t C;                              // list length incl. the diagonal
+  FastDiv f_va, f_vb, f_npv_a, f_npv_b, f_nSb;
   const double* h1e;                       // [n][n]
   const double* S;                         // [i][j][a][b] = (ai|bj)
   const double* J2;                        // [p][q] = (pp|qq)
@@ -54,6 +73,9 @@ struct MadeDev {
   uint32_t boff[kMaxLayers];   // bias offset of layer l (padded to 16 * nob)
   uint32_t nfrag;              // total fragments
   uint32_t nbias;              // total padded biases
+  // BF16 packing stores hidden units sorted by degree; o-block ob of layer l then only
+  // needs its first kend[l][ob] k-blocks (the rest of its weights are masked).
+  uint8_t kend[kMaxLayers][kMaxOutBlocks];
   const void* wfrag;           // packed weights (bf16x8 per lane or double per lane)
   const void* bias;            // float (BF16 mode) or double (FP64 mode)
 };
@@ -120,6 +142,32 @@ __device__ __forceinline__ int first_diff_orbital(const uint64_t (&a)[NW], const
   return k >> 1;
 }
 
+// Hidden unit at position u when the units of a layer of width w are sorted by degree
+// (degree of unit j is (j mod (n-1)) + 1; ties keep ascending j). Returns -1 past w.
+__host__ __device__ inline int sorted_unit(int n, int w, int u) {
+  const int q = n - 1;
+  for (int r = 0; r < q; ++r) {
+    const int cnt = (w > r) ? (w - r - 1) / q + 1 : 0;
+    if (u < cnt) return r + u * q;
+    u -= cnt;
+  }
+  return -1;
+}
+
+// Eight occupation bits starting at bit `pos` (orbitals pos/2 .. pos/2 + 3).
+template <int NW>
+__device__ __forceinline__ uint32_t bits8_at(const uint64_t (&x)[NW], int pos) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if ((pos >> 6) == w) {
+      v = x[w] >> (pos & 63);
+      if (w + 1 < NW && (pos & 63) > 56) v |= x[w + 1] << (64 - (pos & 63));
+    }
+  }
+  return (uint32_t)(v & 0xFFull);
+}
+
 // ----------------------------------------------------------------------------- the generator
 // Kinds of list entries.
 enum : int { KIND_DIAG = 0, KIND_SINGLE = 1, KIND_DOUBLE_SAME = 2, KIND_DOUBLE_AB = 3 };
@@ -142,29 +190,31 @@ __device__ __forceinline__ Excitation unrank(const SysDev& S, const SampleCtx& c
   uint32_t u = t - 1;
   if (u < S.nSa) {
     e.kind = KIND_SINGLE; e.spin = 0; e.sidx = u;
-    e.i = c.occ[0][u / (uint32_t)S.va]; e.a = c.vir[0][u % (uint32_t)S.va];
+    const uint32_t q = fdiv(u, S.f_va);
+    e.i = c.occ[0][q]; e.a = c.vir[0][u - q * S.va];
   } else if ((u -= S.nSa) < S.nSb) {
     e.kind = KIND_SINGLE; e.spin = 1; e.sidx = S.nSa + u;
-    e.i = c.occ[1][u / (uint32_t)S.vb]; e.a = c.vir[1][u % (uint32_t)S.vb];
+    const uint32_t q = fdiv(u, S.f_vb);
+    e.i = c.occ[1][q]; e.a = c.vir[1][u - q * S.vb];
   } else if ((u -= S.nSb) < S.nDaa) {
     e.kind = KIND_DOUBLE_SAME; e.spin = 0;
-    const uint32_t po = u / S.npv_a, pv = u % S.npv_a;
+    const uint32_t po = fdiv(u, S.f_npv_a), pv = u - po * S.npv_a;
     const uint16_t oo = S.pair_oa[po], vv = S.pair_va[pv];
     e.i = c.occ[0][oo & 0xFF]; e.j = c.occ[0][oo >> 8];
     e.a = c.vir[0][vv & 0xFF]; e.b = c.vir[0][vv >> 8];
   } else if ((u -= S.nDaa) < S.nDbb) {
     e.kind = KIND_DOUBLE_SAME; e.spin = 1;
-    const uint32_t po = u / S.npv_b, pv = u % S.npv_b;
+    const uint32_t po = fdiv(u, S.f_npv_b), pv = u - po * S.npv_b;
     const uint16_t oo = S.pair_ob[po], vv = S.pair_vb[pv];
     e.i = c.occ[1][oo & 0xFF]; e.j = c.occ[1][oo >> 8];
     e.a = c.vir[1][vv & 0xFF]; e.b = c.vir[1][vv >> 8];
   } else {
     u -= S.nDbb;
     e.kind = KIND_DOUBLE_AB;
-    const uint32_t nbvb = S.nSb;
-    const uint32_t u1 = u / nbvb, u2 = u % nbvb;
-    e.i = c.occ[0][u1 / (uint32_t)S.va]; e.a = c.vir[0][u1 % (uint32_t)S.va];
-    e.j = c.occ[1][u2 / (uint32_t)S.vb]; e.b = c.vir[1][u2 % (uint32_t)S.vb];
+    const uint32_t u1 = fdiv(u, S.f_nSb), u2 = u - u1 * S.nSb;
+    const uint32_t q1 = fdiv(u1, S.f_va), q2 = fdiv(u2, S.f_vb);
+    e.i = c.occ[0][q1]; e.a = c.vir[0][u1 - q1 * S.va];
+    e.j = c.occ[1][q2]; e.b = c.vir[1][u2 - q2 * S.vb];
   }
   if (e.kind == KIND_SINGLE) {
     e.I = 2 * e.i + e.spin; e.A = 2 * e.a + e.spin;

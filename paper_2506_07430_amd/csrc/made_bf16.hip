@@ -10,9 +10,14 @@
 // In the output layer the four logits of orbital 4*block + g land in one lane, so the
 // number-conserving log-softmax is lane-local.
 //
+// Sparsity: hidden units are packed in ascending degree. A unit of degree m only sees
+// units of degree <= m of the layer below (or the bits of orbitals < m, or, for the
+// logits of orbital p, hidden units of degree <= p), i.e. a prefix in this order, so
+// o-block ob of layer l multiplies only its first kend[l][ob] k-blocks.
+//
 // Precision: layer-0 inputs are exact 0/1; every later activation a (FP32 after bias
 // and ReLU) is fed as hi = bf16(a) plus lo = bf16(a - hi), two MFMAs per weight
-// fragment, so the representation error is ~2^-18 |a|. Accumulation is FP32; the
+// fragment, so the representation error is ~2^-16 |a|. Accumulation is FP32; the
 // ratio exp(dA + i dphi), the matrix element and every sum are FP64.
 #include "elocal_internal.hpp"
 #include "kernels.hpp"
@@ -27,31 +32,38 @@ __device__ __forceinline__ bool made_allowed(int n, int L, int l, int o, int k) 
   return (o / 4) + 1 > (k % nm1) + 1;
 }
 
-// k index (within a layer's input) of k-slot j of lane group g in k-block kb.
+// k index (position within the layer's packed input order) of k-slot j of lane group g.
 __device__ __forceinline__ int kslot_bf16(int l, int kb, int g, int j) {
   if (l == 0) return 32 * kb + 8 * g + j;
   return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
 }
 
+// Packs the caller's parameters (bf16 bit patterns, natural order) into MFMA A-operand
+// fragments with hidden units in degree order, masked entries zeroed; biases to FP32.
 __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict__ theta,
                             bf16x8* __restrict__ frag, float* __restrict__ bias) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t nlane = M.nfrag * 64u;
-  if (gid < nlane) {
+  const int n = M.n, L = M.L;
+  if (gid < M.nfrag * 64u) {
     const uint32_t f = gid >> 6;
     const int lane = gid & 63;
     int l = 0;
-    while (l < M.L && f >= M.woff[l + 1]) ++l;
+    while (l < L && f >= M.woff[l + 1]) ++l;
     const uint32_t local = f - M.woff[l];
     const int ob = local / M.nk[l], kb = local % M.nk[l];
-    const int o = 16 * ob + (lane & 15), g = lane >> 4;
+    const int orow = 16 * ob + (lane & 15), g = lane >> 4;
+    // original output unit of this row
+    const int o = (l < L) ? (orow < M.nout[l] ? sorted_unit(n, M.nout[l], orow) : -1)
+                          : (orow < M.nout[l] ? orow : -1);
     unsigned short v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = kslot_bf16(l, kb, g, j);
+      const int kpos = kslot_bf16(l, kb, g, j);
+      int k = -1;
+      if (kpos < M.nin[l]) k = (l == 0) ? kpos : sorted_unit(n, M.nin[l], kpos);
       unsigned short bits = 0;
-      if (o < M.nout[l] && k < M.nin[l] && made_allowed(M.n, M.L, l, o, k)) {
-        if (l == M.L && o == 4 * M.n) bits = theta[T.offwphi + k];
+      if (o >= 0 && k >= 0 && made_allowed(n, L, l, o, k)) {
+        if (l == L && o == 4 * n) bits = theta[T.offwphi + k];
         else bits = theta[T.offW[l] + (uint32_t)o * M.nin[l] + k];
       }
       v[j] = bits;
@@ -62,10 +74,13 @@ __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict
   }
   if (gid < M.nbias) {
     int l = 0;
-    while (l < M.L && gid >= M.boff[l + 1]) ++l;
-    const int o = gid - M.boff[l];
+    while (l < L && gid >= M.boff[l + 1]) ++l;
+    const int orow = gid - M.boff[l];
     unsigned short bits = 0;
-    if (o < M.nout[l]) bits = (l == M.L && o == 4 * M.n) ? theta[T.offbphi] : theta[T.offb[l] + o];
+    if (orow < M.nout[l]) {
+      if (l < L) bits = theta[T.offb[l] + sorted_unit(n, M.nout[l], orow)];
+      else bits = (orow == 4 * n) ? theta[T.offbphi] : theta[T.offb[l] + orow];
+    }
     bias[gid] = __uint_as_float((uint32_t)bits << 16);
   }
 }
@@ -80,25 +95,38 @@ __device__ __forceinline__ bf16x8 bits_to_bf16x8(uint32_t v) {
   return r;
 }
 
-template <int NW>
-__device__ __forceinline__ uint32_t byte_at(const uint64_t (&x)[NW], int bit) {
-  uint32_t v = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w)
-    if ((bit >> 6) == w) v = (uint32_t)((x[w] >> (bit & 63)) & 0xFFull);
-  return v;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of a pair, then hi = bf16(a) (one packed convert) and lo = bf16(a - hi); the
+// FP32 value of hi is recovered from its bits, so each element costs four VALU ops.
+__device__ __forceinline__ void split_pair(float u, float v, uint32_t& hi, uint32_t& lo) {
+  u = __int_as_float(max(__float_as_int(u), 0));     // ReLU: negative floats are negative ints
+  v = __int_as_float(max(__float_as_int(v), 0));
+  bf16x2 h;
+  h[0] = (__bf16)u;
+  h[1] = (__bf16)v;
+  uint32_t hb;
+  __builtin_memcpy(&hb, &h, 4);
+  const float uh = __uint_as_float(hb << 16), vh = __uint_as_float(hb & 0xFFFF0000u);
+  bf16x2 l;
+  l[0] = (__bf16)(u - uh);
+  l[1] = (__bf16)(v - vh);
+  __builtin_memcpy(&lo, &l, 4);
+  hi = hb;
 }
 
+// Units 4g..4g+3 of block a and of block a+1 -> the 8 k-slots of the next layer.
 __device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float u = fmaxf(a[i], 0.f), v = fmaxf(b[i], 0.f);
-    const __bf16 uh = (__bf16)u, vh = (__bf16)v;
-    hi[i] = uh; hi[4 + i] = vh;
-    lo[i] = (__bf16)(u - (float)uh);
-    lo[4 + i] = (__bf16)(v - (float)vh);
-  }
+  uint32_t h[4], l[4];
+  split_pair(a[0], a[1], h[0], l[0]);
+  split_pair(a[2], a[3], h[1], l[1]);
+  split_pair(b[0], b[1], h[2], l[2]);
+  split_pair(b[2], b[3], h[3], l[3]);
+  __builtin_memcpy(&hi, h, 16);
+  __builtin_memcpy(&lo, l, 16);
 }
+
+__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ f32x4 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -110,12 +138,35 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
   return r;
 }
 
+// Output block ob of the last layer for both column blocks (rows r and 16 + r).
+template <int KB>
+__device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ W,
+                                          const float* __restrict__ bias, const bf16x8 (&chi)[2][KB],
+                                          const bf16x8 (&clo)[2][KB], int ob, int lane, f32x4 (&a)[2]) {
+  const int l = M.L, nk = M.nk[l], ke = sgpr(M.kend[l][ob]);
+  a[0] = a[1] = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
+  const bf16x8* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb < ke) {
+      const bf16x8 w = wp[kb * 64];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        a[c] = mfma_bf16(w, chi[c][kb], a[c]);
+        a[c] = mfma_bf16(w, clo[c][kb], a[c]);
+      }
+    }
+  }
+}
+
 // Runs the network on two 16-row column blocks (rows r and 16 + r of lane r) and calls
-// epi(ob, acc_c0, acc_c1) for every 16-unit block of the output layer.
+// epi(ob, acc_c0, acc_c1) for the output blocks ob >= ob_first (earlier blocks belong
+// to orbitals the caller does not need).
 template <int HMAX, int NW, class Epi>
 __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restrict__ W,
                                          const float* __restrict__ bias,
-                                         const uint64_t (&xr)[2][NW], int lane, Epi&& epi) {
+                                         const uint64_t (&xr)[2][NW], int lane, int ob_first,
+                                         Epi&& epi) {
   constexpr int KB = HMAX / 32;
   const int g = lane >> 4;
   bf16x8 chi[2][KB], clo[2][KB];
@@ -127,23 +178,26 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
-        xin[c][kb] = bits_to_bf16x8(kb < nk ? byte_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
+        xin[c][kb] = bits_to_bf16x8(kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
+        const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
         f32x4 a0[2], a1[2];
-        const f32x4 b0 = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
-        const f32x4 b1 = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
-        a0[0] = a0[1] = b0; a1[0] = a1[1] = b1;
+        a0[0] = a0[1] = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
+        a1[0] = a1[1] = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
+        const bf16x8* w0p = W + (size_t)(M.woff[0] + (2 * kbo) * nk) * 64 + lane;
+        const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          if (kb < nk) {
-            const bf16x8 w0 = W[(M.woff[0] + (2 * kbo) * nk + kb) * 64 + lane];
-            const bf16x8 w1 = W[(M.woff[0] + (2 * kbo + 1) * nk + kb) * 64 + lane];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              a0[c] = mfma_bf16(w0, xin[c][kb], a0[c]);
-              a1[c] = mfma_bf16(w1, xin[c][kb], a1[c]);
+          if (kb < ke1) {
+            const bf16x8 w1 = w1p[kb * 64];
+            a1[0] = mfma_bf16(w1, xin[0][kb], a1[0]);
+            a1[1] = mfma_bf16(w1, xin[1][kb], a1[1]);
+            if (kb < ke0) {
+              const bf16x8 w0 = w0p[kb * 64];
+              a0[0] = mfma_bf16(w0, xin[0][kb], a0[0]);
+              a0[1] = mfma_bf16(w0, xin[1][kb], a0[1]);
             }
           }
         }
@@ -159,21 +213,28 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
+        const int ke0 = sgpr(M.kend[l][2 * kbo]), ke1 = sgpr(M.kend[l][2 * kbo + 1]);
         f32x4 a0[2], a1[2];
-        const f32x4 b0 = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
-        const f32x4 b1 = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
-        a0[0] = a0[1] = b0; a1[0] = a1[1] = b1;
+        a0[0] = a0[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
+        a1[0] = a1[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
+        const bf16x8* w0p = W + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
+        const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-          if (kb < nk) {
-            const bf16x8 w0 = W[(M.woff[l] + (2 * kbo) * nk + kb) * 64 + lane];
-            const bf16x8 w1 = W[(M.woff[l] + (2 * kbo + 1) * nk + kb) * 64 + lane];
+          if (kb < ke1) {
+            const bf16x8 w1 = w1p[kb * 64];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-              a0[c] = mfma_bf16(w0, chi[c][kb], a0[c]);
-              a0[c] = mfma_bf16(w0, clo[c][kb], a0[c]);
               a1[c] = mfma_bf16(w1, chi[c][kb], a1[c]);
               a1[c] = mfma_bf16(w1, clo[c][kb], a1[c]);
+            }
+            if (kb < ke0) {
+              const bf16x8 w0 = w0p[kb * 64];
+#pragma unroll
+              for (int c = 0; c < 2; ++c) {
+                a0[c] = mfma_bf16(w0, chi[c][kb], a0[c]);
+                a0[c] = mfma_bf16(w0, clo[c][kb], a0[c]);
+              }
             }
           }
         }
@@ -186,57 +247,85 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) { chi[c][kb] = nhi[c][kb]; clo[c][kb] = nlo[c][kb]; }
   }
-  // ---- output layer: 4n logits + phase row, block by block into the epilogue
+  // ---- output layer, block by block into the epilogue
   {
-    const int l = M.L, nk = M.nk[l], nob = M.nob[l];
+    const int nob = M.nob[M.L];
 #pragma unroll 1
-    for (int ob = 0; ob < nob; ++ob) {
-      f32x4 a[2];
-      a[0] = a[1] = load_bias4(bias, M.boff[l] + 16 * ob + 4 * g);
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        if (kb < nk) {
-          const bf16x8 w = W[(M.woff[l] + ob * nk + kb) * 64 + lane];
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            a[c] = mfma_bf16(w, chi[c][kb], a[c]);
-            a[c] = mfma_bf16(w, clo[c][kb], a[c]);
-          }
-        }
-      }
-      epi(ob, a[0], a[1]);
+    for (int ob = sgpr(ob_first); ob < nob; ++ob) {
+      f32x4 acc[2];
+      out_block<KB>(M, W, bias, chi, clo, ob, lane, acc);
+      epi(ob, acc[0], acc[1]);
     }
   }
 }
 
-// log p_p(s) of the occupation s of orbital p in row x (FP32 log-softmax over the
-// occupations that keep both electron counts reachable).
+// Per-row state of the epilogue: electrons of each spin in the orbitals before the
+// lane's next orbital (advanced by four orbitals per output block).
+struct RowCounts {
+  int cu, cd;
+};
+
 template <int NW>
-__device__ __forceinline__ float cond_logp(const uint64_t (&x)[NW], int p, int n, int na, int nb,
-                                           const f32x4& z) {
-  const int cu = count_spin_below<NW>(x, p, 0), cd = count_spin_below<NW>(x, p, 1);
+__device__ __forceinline__ RowCounts counts_before(const uint64_t (&x)[NW], int p) {
+  RowCounts r;
+  r.cu = count_spin_below<NW>(x, p, 0);
+  r.cd = count_spin_below<NW>(x, p, 1);
+  return r;
+}
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kLn2 = 0.6931471805599453094;
+
+// log2 p_p(s_p) for orbital p of row x, and advance the counts past orbitals p..p+3.
+// The softmax runs over the occupations that keep both electron counts reachable,
+// in base 2 on the native exp2/log2 units (one rescale to natural log per row, by the
+// caller); the exponentials are taken unshifted unless their sum leaves [1e-30, 1e30].
+template <int NW>
+__device__ __forceinline__ float cond_log2p_step(const uint64_t (&x)[NW], int p, int n, int na, int nb,
+                                                 const f32x4& z, RowCounts& rc) {
+  const uint32_t b8 = bits8_at<NW>(x, 2 * p);
+  const uint32_t s = b8 & 3u;
   const int left = n - p - 1;
-  const int s = getbit<NW>(x, 2 * p) + 2 * getbit<NW>(x, 2 * p + 1);
-  bool ok[4];
-  float m = -INFINITY;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int u = cu + (q & 1), d = cd + (q >> 1);
-    ok[q] = (u <= na) && (d <= nb) && (u + left >= na) && (d + left >= nb);
-    if (ok[q]) m = fmaxf(m, z[q]);
+  const int ra = na - rc.cu, rb = nb - rc.cd;
+  const bool a_must = ra > left, a_may = ra > 0;
+  const bool b_must = rb > left, b_may = rb > 0;
+  const bool ok0 = !a_must && !b_must, ok1 = a_may && !b_must;
+  const bool ok2 = !a_must && b_may, ok3 = a_may && b_may;
+  const float y0 = z[0] * kLog2e, y1 = z[1] * kLog2e, y2 = z[2] * kLog2e, y3 = z[3] * kLog2e;
+  const float e0 = ok0 ? __builtin_amdgcn_exp2f(y0) : 0.f;
+  const float e1 = ok1 ? __builtin_amdgcn_exp2f(y1) : 0.f;
+  const float e2 = ok2 ? __builtin_amdgcn_exp2f(y2) : 0.f;
+  const float e3 = ok3 ? __builtin_amdgcn_exp2f(y3) : 0.f;
+  const float sum = (e0 + e1) + (e2 + e3);
+  float lse = __builtin_amdgcn_logf(sum);
+  if (__builtin_expect(!(sum > 1e-30f && sum < 1e30f), 0)) {
+    float m = -INFINITY;
+    m = ok0 ? fmaxf(m, y0) : m;
+    m = ok1 ? fmaxf(m, y1) : m;
+    m = ok2 ? fmaxf(m, y2) : m;
+    m = ok3 ? fmaxf(m, y3) : m;
+    float t = (ok0 ? __builtin_amdgcn_exp2f(y0 - m) : 0.f) + (ok1 ? __builtin_amdgcn_exp2f(y1 - m) : 0.f) +
+              (ok2 ? __builtin_amdgcn_exp2f(y2 - m) : 0.f) + (ok3 ? __builtin_amdgcn_exp2f(y3 - m) : 0.f);
+    lse = m + __builtin_amdgcn_logf(t);
   }
-  float sum = 0.f;
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (ok[q]) sum += __expf(z[q] - m);
-  const float zs = (s == 0) ? z[0] : (s == 1) ? z[1] : (s == 2) ? z[2] : z[3];
-  return zs - m - __logf(sum);
+  const float y01 = (s & 1u) ? y1 : y0;
+  const float y23 = (s & 1u) ? y3 : y2;
+  const float ys = (s & 2u) ? y23 : y01;
+  rc.cu += __popc(b8 & 0x55u);
+  rc.cd += __popc(b8 & 0xAAu);
+  return ys - lse;
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
 }
 
 // ----------------------------------------------------------------------------- sample pass
@@ -263,14 +352,15 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
-  mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, [&](int ob, const f32x4& a0, const f32x4& a1) {
+  RowCounts rc[2] = {counts_before<NW>(xr[0], g), counts_before<NW>(xr[1], g)};
+  mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, 0, [&](int ob, const f32x4& a0, const f32x4& a1) {
     const int p = 4 * ob + g;
     if (p < n) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const float lp = cond_logp<NW>(xr[c], p, n, na, nb, c ? a1 : a0);
+        const float lp = cond_log2p_step<NW>(xr[c], p, n, na, nb, c ? a1 : a0, rc[c]);
         A[c] += (double)lp;
-        if (rb[c] < P.B) P.lpx[rb[c] * n + p] = lp;
+        if (rb[c] < P.B) P.lpx[rb[c] * n + p] = lp;     // log2 units
       }
     }
     if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
@@ -287,7 +377,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
       P.zphi[rb[c]] = (double)zp[c];
       if (P.logpsi) {
         const double sig = 1.0 / (1.0 + exp(-(double)zp[c]));
-        P.logpsi[2 * rb[c]] = 0.5 * A[c];
+        P.logpsi[2 * rb[c]] = 0.5 * kLn2 * A[c];
         P.logpsi[2 * rb[c] + 1] = 2.0 * M_PI * sig;
       }
     }
@@ -297,11 +387,15 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
 // ----------------------------------------------------------------------------- fused eval
 struct WaveCtxBF16 {
   SampleCtx c;
-  float lpx[kMaxOrb];
+  float lpx[kMaxOrb];   // log2 p_p(s_p) of the sample
 };
 
+// One work item = one sample and P.tpi consecutive groups of 64 list entries. Per group:
+// every lane generates one entry (x', H_{x'x} in FP64, first changed orbital); the
+// network runs twice on 32 of them; every lane then forms H exp(dA + i dphi) in FP64
+// for its own entry. Partial sums are per item, in a fixed order.
 template <int HMAX, int NW, bool LDSW>
-__global__ void __launch_bounds__(256) k_eval_bf16(EvalArgs P) {
+__global__ void __launch_bounds__(256, (HMAX <= 128 ? 2 : 1)) k_eval_bf16(EvalArgs P) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
   const MadeDev& M = P.made;
@@ -342,58 +436,72 @@ __global__ void __launch_bounds__(256) k_eval_bf16(EvalArgs P) {
       cur_b = b;
     }
     double acc_re = 0.0, acc_im = 0.0;
-    for (uint32_t tile = 0; tile < P.tpi; ++tile) {
-      const uint32_t t0 = 1u + (seg * P.tpi + tile) * 32u;
+    for (uint32_t grp = 0; grp < P.tpi; ++grp) {
+      const uint32_t t0 = 1u + (seg * P.tpi + grp) * 64u;
       if (t0 >= S.C) break;
-      const uint32_t t = t0 + (lane & 31);
-      uint64_t xp[NW];
+      // ---- generate this lane's entry
+      const uint32_t t = t0 + lane;
+      uint64_t xo[NW];
       double hv = 0.0;
       if (t < S.C) {
         const Excitation e = unrank(S, wc.c, t);
-        const int sg = apply_excitation<NW>(xs, e, xp);
-        if (lane < 32) {
-          const double v = excitation_value(S, e, Fs, ed);
-          hv = sg < 0 ? -v : v;
-        }
+        const int sg = apply_excitation<NW>(xs, e, xo);
+        const double v = excitation_value(S, e, Fs, ed);
+        hv = sg < 0 ? -v : v;
       } else {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) xp[w] = xs[w];
+        for (int w = 0; w < NW; ++w) xo[w] = xs[w];
       }
-      uint64_t xr[2][NW];
-      const bool own1 = (lane >> 4) & 1;
+      const int p0o = first_diff_orbital<NW>(xs, xo, n);
+      const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
+      double dA_own = 0.0;
+      float zp_own = 0.f;
+      // ---- network on entries 32h .. 32h + 31
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const uint64_t other = __shfl_xor(xp[w], 16);
-        xr[0][w] = own1 ? other : xp[w];
-        xr[1][w] = own1 ? xp[w] : other;
-      }
-      const int p0[2] = {first_diff_orbital<NW>(xs, xr[0], n), first_diff_orbital<NW>(xs, xr[1], n)};
-      double dA[2] = {0.0, 0.0};
-      float zp[2] = {0.f, 0.f};
-      mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, [&](int ob, const f32x4& a0, const f32x4& a1) {
-        const int p = 4 * ob + g;
-        if (p < n) {
-          const float lx = wc.lpx[p];
+      for (int h = 0; h < 2; ++h) {
+        uint64_t xr[2][NW];
+        int p0[2];
 #pragma unroll
-          for (int c = 0; c < 2; ++c)
-            if (p >= p0[c]) dA[c] += (double)(cond_logp<NW>(xr[c], p, n, na, nb, c ? a1 : a0) - lx);
+        for (int c = 0; c < 2; ++c) {
+          const int src = 32 * h + 16 * c + r16;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) xr[c][w] = __shfl(xo[w], src);
+          p0[c] = __shfl(p0o, src);
         }
-        if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
-      });
+        double dA[2] = {0.0, 0.0};
+        float zp[2] = {0.f, 0.f};
+        const int pfirst = 4 * ob_first + g;
+        RowCounts rc[2] = {counts_before<NW>(xr[0], pfirst), counts_before<NW>(xr[1], pfirst)};
+        mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
+          const int p = 4 * ob + g;
+          if (p < n) {
+            const float lx = wc.lpx[p];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        dA[c] += __shfl_xor(dA[c], 16);
-        dA[c] += __shfl_xor(dA[c], 32);
-        zp[c] = __shfl(zp[c], g_phi * 16 + r16);
+            for (int c = 0; c < 2; ++c) {
+              const float lp = cond_log2p_step<NW>(xr[c], p, n, na, nb, c ? a1 : a0, rc[c]);
+              dA[c] += (double)(p >= p0[c] ? lp - lx : 0.f);
+            }
+          }
+          if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
+        });
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          dA[c] += __shfl_xor(dA[c], 16);
+          dA[c] += __shfl_xor(dA[c], 32);
+          zp[c] = __shfl(zp[c], g_phi * 16 + r16);
+        }
+        if ((lane >> 5) == h) {
+          const int c = (lane >> 4) & 1;
+          dA_own = c ? dA[1] : dA[0];
+          zp_own = c ? zp[1] : zp[0];
+        }
       }
-      if (lane < 32) {
-        const int c = lane >> 4;
-        const double da = 0.5 * (c ? dA[1] : dA[0]);
-        const double z = (double)(c ? zp[1] : zp[0]);
-        const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-z)) - sig_x);
+      // ---- FP64 ratio and accumulation, one entry per lane
+      if (t < S.C) {
+        const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-(double)zp_own)) - sig_x);
         double sn, cs;
         sincos(dphi, &sn, &cs);
-        const double mag = hv * exp(da);
+        const double mag = hv * exp((0.5 * kLn2) * dA_own);
         acc_re += mag * cs;
         acc_im += mag * sn;
       }
