@@ -40,9 +40,9 @@
  * Errors: every call returns elocal_status; a non-zero status leaves the outputs
  *   unspecified and the handle usable. elocal_last_error() gives a message for the
  *   calling thread's last failure.
- * Threads: a handle is read-only after elocal_create (except for the timing calls at
- *   the end of this file); concurrent calls on one handle with separate workspaces
- *   and outputs are allowed.
+ * Threads: a handle is read-only after elocal_create (except for the timing and tuning
+ *   calls at the end of this file); concurrent calls on one handle with separate
+ *   workspaces and outputs are allowed.
  */
 #ifndef ELOCAL_H
 #define ELOCAL_H
@@ -196,6 +196,17 @@ elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* 
  */
 elocal_status elocal_timing_enable(elocal_t h, int on);
 elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launches, int reset);
+
+/*
+ * Launch shape of the fused local-energy kernel (for the autotuner). A value <= 0
+ * restores the built-in choice. ELOCAL_TUNE_GRID: blocks of 4 waves (persistent
+ * grid-stride loop over work items); ELOCAL_TUNE_GROUPS: list-entry groups per work
+ * item (64 entries per group in BF16 mode, 16 in FP64 mode). Results do not depend on
+ * the launch shape except through the fixed per-item summation order (rounding only).
+ * Mutates the handle: do not overlap with other calls on it.
+ */
+enum { ELOCAL_TUNE_GRID = 0, ELOCAL_TUNE_GROUPS = 1 };
+elocal_status elocal_tune(elocal_t h, int param, int64_t value);
 
 /* Message for the calling thread's last failure ("" if none). */
 const char* elocal_last_error(void);

@@ -80,6 +80,9 @@ struct elocal_ctx {
   std::vector<hipEvent_t> ev_start, ev_stop;
   int64_t recorded = 0;   // pairs recorded since the last reset
   int64_t ring_pos = 0;
+  // launch-shape overrides of the fused kernel (<= 0: built-in)
+  int64_t tune_grid = 0;
+  int64_t tune_groups = 0;
 };
 
 namespace {
@@ -185,6 +188,7 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
   // BF16: groups of 64 entries (one per lane), 8 per item; FP64: tiles of 16, 16 per item
   p.rows_per_tile = (G.precision == ELOCAL_BF16) ? 64 : 16;
   p.tpi = (G.precision == ELOCAL_BF16) ? 8 : 16;
+  if (h->tune_groups > 0) p.tpi = (uint32_t)std::min<int64_t>(h->tune_groups, 1 << 16);
   const uint64_t rows = h->sys.C - 1;   // the diagonal entry needs no ansatz call
   const uint64_t per_item = (uint64_t)p.rows_per_tile * p.tpi;
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
@@ -199,7 +203,7 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
     p.lds = 0;
   }
   const int64_t want = (p.n_items + 3) / 4;
-  const int64_t cap = (int64_t)h->cu_count * 8;
+  const int64_t cap = h->tune_grid > 0 ? std::min<int64_t>(h->tune_grid, 1 << 20) : (int64_t)h->cu_count * 8;
   p.grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
   return p;
 }
@@ -556,6 +560,15 @@ elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launch
   *launches = n;
   if (reset) h->recorded = 0;
   return ELOCAL_OK;
+}
+
+elocal_status elocal_tune(elocal_t h, int param, int64_t value) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  switch (param) {
+    case ELOCAL_TUNE_GRID: h->tune_grid = value; return ELOCAL_OK;
+    case ELOCAL_TUNE_GROUPS: h->tune_groups = value; return ELOCAL_OK;
+  }
+  return fail(ELOCAL_E_INVALID, "unknown tuning parameter %d", param);
 }
 
 elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B, void* ws,

@@ -65,8 +65,9 @@ def lib():
         L.elocal_last_error.restype = ctypes.c_char_p
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
+        L.elocal_tune.argtypes = [vp, i32, i64]
         for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
-                  "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing"):
+                  "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -75,7 +76,7 @@ def lib():
 def exported_symbols() -> Sequence[str]:
     return ["elocal_create", "elocal_destroy", "elocal_num_connected", "elocal_words", "elocal_num_params",
             "elocal_workspace_bytes", "elocal_connect", "elocal_eval", "elocal_stats", "elocal_grad",
-            "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_last_error"]
+            "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune", "elocal_last_error"]
 
 
 def _check(status: int):
@@ -220,6 +221,11 @@ class Hamiltonian:
         n = ctypes.c_int64(0)
         _check(lib().elocal_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(reset)))
         return ms.value, int(n.value)
+
+    def tune(self, grid: int = 0, groups: int = 0):
+        """Launch shape of the fused kernel (0 = built-in)."""
+        _check(lib().elocal_tune(self._h, 0, int(grid)))
+        _check(lib().elocal_tune(self._h, 1, int(groups)))
 
     def check_samples(self, x: torch.Tensor, stream=None) -> int:
         x = self._x(x)
