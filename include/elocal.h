@@ -158,6 +158,28 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a,
                           double* eloc, double* logpsi);
 
 /*
+ * Local energies of several systems in one persistent launch (Methods: the batch of a
+ * training step split over independent summands; here systems of different size whose
+ * connected lists differ in length by orders of magnitude).
+ * n_sys in [1, ELOCAL_MAX_SYSTEMS]; hs, a, x, B, eloc, logpsi are HOST arrays of
+ * n_sys entries (the pointers they hold are device memory, as in elocal_eval; logpsi
+ * itself or any of its entries may be NULL). Every handle must belong to the current
+ * device and every ansatz must have the same precision. System s gets exactly the
+ * eloc[s] (and logpsi[s]) that elocal_eval(hs[s], ..., a[s], x[s], B[s]) gives: the
+ * per-sample work and its summation order are the same; only the scheduling differs
+ * (the fused kernel runs once over the work items of all systems, ordered by cost per
+ * item, so no system leaves a tail of idle compute units behind it).
+ * ws needs elocal_workspace_bytes_multi(...) bytes.
+ */
+enum { ELOCAL_MAX_SYSTEMS = 16 };
+size_t elocal_workspace_bytes_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* const* a,
+                                    const int64_t* B);
+elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s,
+                                const elocal_ansatz* const* a, const uint64_t* const* x,
+                                const int64_t* B, void* ws, size_t ws_bytes, double* const* eloc,
+                                double* const* logpsi);
+
+/*
  * Energy statistics (Methods, batch estimator): stats[4] = (Re<E>, Im<E>,
  * sum_i w_i |E_i - <E>|^2 / sum_i w_i, sum_i w_i), from eloc [B][2] and w [B]
  * (device). B >= 1; sum w must be > 0. Fixed-order FP64 reduction.
@@ -188,8 +210,9 @@ elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* 
 
 /*
  * Timing of the dominant kernel (the fused local-energy kernel of elocal_eval).
- * When enabled, each elocal_eval on the handle records a pair of HIP events around
- * that kernel on the caller's stream (a ring of 1024 pairs, reused in order).
+ * When enabled, each elocal_eval on the handle (and each elocal_eval_multi whose first
+ * handle it is) records a pair of HIP events around that kernel on the caller's stream
+ * (a ring of 1024 pairs, reused in order).
  * elocal_kernel_timing waits for the recorded events, returns the summed milliseconds
  * and the number of launches recorded since the last reset (reset != 0 clears them).
  * These two calls mutate the handle: do not overlap them with other calls on it.

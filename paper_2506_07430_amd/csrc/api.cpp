@@ -180,8 +180,19 @@ struct EvalPlan {
   int64_t n_items;
   bool ldsw;
   size_t lds;
+  int waves;        // waves per block
   unsigned grid;
 };
+
+constexpr size_t kLdsBytes = 160 * 1024;
+// per-wave LDS context of the BF16 kernel: occupied/virtual lists + log2 p of the sample
+constexpr size_t kCtxBytesBF16 = kMaxEvalWavesBF16 * (sizeof(SampleCtx) + kMaxOrb * sizeof(float));
+
+// Persistent grid: 32 waves per CU in total (a few rounds of resident blocks), unless tuned.
+int64_t grid_cap(const elocal_ctx* h, int waves) {
+  if (h->tune_grid > 0) return std::min<int64_t>(h->tune_grid, 1 << 20);
+  return (int64_t)h->cu_count * (32 / waves);
+}
 
 EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
   EvalPlan p{};
@@ -194,17 +205,17 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
   p.n_items = (int64_t)p.ips * B;
   if (G.precision == ELOCAL_BF16) {
-    const size_t ctx = 4 * (sizeof(SampleCtx) + kMaxOrb * sizeof(float));
-    const size_t need = align256(G.wbytes) + align256(G.bbytes) + ctx;
-    p.ldsw = need <= 81920;   // two 4-wave blocks per CU (160 KiB LDS)
-    p.lds = p.ldsw ? need : ctx;
+    const size_t need = align256(G.wbytes) + align256(G.bbytes) + kCtxBytesBF16;
+    p.ldsw = need <= kLdsBytes;   // one 8-wave block per CU owns the CU's LDS
+    p.lds = p.ldsw ? need : kCtxBytesBF16;
+    p.waves = eval_waves_bf16(G.hmax);
   } else {
     p.ldsw = false;
     p.lds = 0;
+    p.waves = 4;
   }
-  const int64_t want = (p.n_items + 3) / 4;
-  const int64_t cap = h->tune_grid > 0 ? std::min<int64_t>(h->tune_grid, 1 << 20) : (int64_t)h->cu_count * 8;
-  p.grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
+  const int64_t want = (p.n_items + p.waves - 1) / p.waves;
+  p.grid = (unsigned)std::max<int64_t>(1, std::min(want, grid_cap(h, p.waves)));
   return p;
 }
 
@@ -502,6 +513,166 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
     h->recorded++;
   }
   HIP_TRY(launch_reduce(w.ediag, w.partial, B, p.ips, eloc, st), "reduce launch");
+  return ELOCAL_OK;
+}
+
+namespace {
+
+// Layout and launch plan of elocal_eval_multi: per-system eval workspaces back to back,
+// then the device copies of the per-system kernel arguments and the item prefix.
+struct MultiPlan {
+  AnsatzGeom G[ELOCAL_MAX_SYSTEMS];
+  EvalPlan p[ELOCAL_MAX_SYSTEMS];
+  size_t off[ELOCAL_MAX_SYSTEMS];   // byte offset of system s's eval workspace
+  int order[ELOCAL_MAX_SYSTEMS];    // position in the item space -> system
+  size_t args_off, first_off, bytes;
+  int64_t first[ELOCAL_MAX_SYSTEMS + 1];
+  int hmax, precision;
+  bool ldsw;            // BF16: every system's weights fit in LDS
+  uint32_t bias_off, ctx_off;
+  size_t lds;
+  unsigned grid;
+};
+
+// the kernels index a plain array EvalArgs[n_sys]
+constexpr size_t kArgsStride = sizeof(EvalArgs);
+static_assert(sizeof(EvalArgs) % 8 == 0, "EvalArgs is stored in 4-byte words");
+
+elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* const* a, const int64_t* B,
+                         MultiPlan& M) {
+  if (n_sys < 1 || n_sys > ELOCAL_MAX_SYSTEMS)
+    return fail(ELOCAL_E_INVALID, "n_sys=%d outside [1, %d]", n_sys, (int)ELOCAL_MAX_SYSTEMS);
+  if (!hs || !a || !B) return fail(ELOCAL_E_INVALID, "null array argument");
+  M.hmax = 0;
+  size_t off = 0;
+  double cost[ELOCAL_MAX_SYSTEMS];
+  for (int s = 0; s < n_sys; ++s) {
+    if (!hs[s]) return fail(ELOCAL_E_INVALID, "handle %d is null", s);
+    if (hs[s]->dev != hs[0]->dev) return fail(ELOCAL_E_INVALID, "handles %d and 0 are on different devices", s);
+    if (B[s] < 0) return fail(ELOCAL_E_INVALID, "B[%d]=%lld is negative", s, (long long)B[s]);
+    if (elocal_status e = make_geom(hs[s], a[s], M.G[s])) return e;
+    if (s > 0 && M.G[s].precision != M.G[0].precision)
+      return fail(ELOCAL_E_INVALID, "ansatz %d has another precision than ansatz 0", s);
+    M.hmax = std::max(M.hmax, M.G[s].hmax);
+    M.p[s] = plan_eval(hs[s], M.G[s], B[s]);
+    M.off[s] = off;
+    off = align256(off + carve_eval(hs[s], M.G[s], M.p[s], B[s], nullptr).bytes);
+    // cost of one item ~ rows x dense multiply-adds per row
+    double per_row = 0.0;
+    const MadeDev& md = M.G[s].md;
+    for (int l = 0; l <= md.L; ++l) per_row += (double)md.nin[l] * md.nout[l];
+    cost[s] = per_row * M.p[s].rows_per_tile * M.p[s].tpi;
+    M.order[s] = s;
+  }
+  M.precision = M.G[0].precision;
+  // most expensive items first: the grid's last items are then the cheapest ones
+  std::stable_sort(M.order, M.order + n_sys, [&](int u, int v) { return cost[u] > cost[v]; });
+  // BF16: index space of chunks (one item per wave of a block, never two systems in a
+  // chunk); FP64: index space of items
+  const int unit = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax) : 1;
+  M.first[0] = 0;
+  for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
+  size_t wmax = 0, bmax = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    wmax = std::max(wmax, align256(M.G[s].wbytes));
+    bmax = std::max(bmax, align256(M.G[s].bbytes));
+  }
+  if (M.precision == ELOCAL_BF16) {
+    M.ldsw = wmax + bmax + kCtxBytesBF16 <= kLdsBytes;
+    M.bias_off = M.ldsw ? (uint32_t)wmax : 0;
+    M.ctx_off = M.ldsw ? (uint32_t)(wmax + bmax) : 0;
+    M.lds = M.ctx_off + kCtxBytesBF16;
+  } else {
+    M.ldsw = false;
+    M.bias_off = M.ctx_off = 0;
+    M.lds = 0;
+  }
+  M.args_off = off;
+  off = align256(off + kArgsStride * n_sys);
+  M.first_off = off;
+  off = align256(off + sizeof(int64_t) * (n_sys + 1));
+  M.bytes = off;
+  const int waves = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax) : 4;
+  const int64_t want = (M.precision == ELOCAL_BF16) ? M.first[n_sys] : (M.first[n_sys] + 3) / 4;
+  M.grid = (unsigned)std::max<int64_t>(1, std::min(want, grid_cap(hs[0], waves)));
+  return ELOCAL_OK;
+}
+
+}  // namespace
+
+size_t elocal_workspace_bytes_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* const* a,
+                                    const int64_t* B) {
+  MultiPlan M;
+  if (plan_multi(n_sys, hs, a, B, M) != ELOCAL_OK) return 0;
+  return M.bytes;
+}
+
+elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, const elocal_ansatz* const* a,
+                                const uint64_t* const* x, const int64_t* B, void* ws, size_t ws_bytes,
+                                double* const* eloc, double* const* logpsi) {
+  MultiPlan M;
+  if (elocal_status e = plan_multi(n_sys, hs, a, B, M)) return e;
+  if (!x || !eloc) return fail(ELOCAL_E_INVALID, "null array argument");
+  if (!ws) return fail(ELOCAL_E_INVALID, "workspace is null");
+  for (int i = 0; i < n_sys; ++i)
+    if (B[i] > 0 && (!a[i]->theta || !x[i] || !eloc[i])) return fail(ELOCAL_E_INVALID, "null pointer for system %d", i);
+  if (ws_bytes < M.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, M.bytes);
+  if (elocal_status st = check_device(hs[0])) return st;
+  hipStream_t st = (hipStream_t)s;
+  char* base = (char*)ws;
+  EvalArgs* d_args = (EvalArgs*)(base + M.args_off);
+  int64_t* d_first = (int64_t*)(base + M.first_off);
+  EvalWs W[ELOCAL_MAX_SYSTEMS];
+  // per-system sample passes (packing, diagonal/Fock terms, ansatz at the samples)
+  for (int i = 0; i < n_sys; ++i) {
+    const elocal_ctx* h = hs[i];
+    const AnsatzGeom& G = M.G[i];
+    W[i] = carve_eval(h, G, M.p[i], B[i], base + M.off[i]);
+    if (B[i] == 0) continue;
+    MadeDev md = G.md;
+    md.wfrag = W[i].frag;
+    md.bias = W[i].bias;
+    if (G.precision == ELOCAL_BF16)
+      HIP_TRY(launch_pack_bf16(md, G.T, (const uint16_t*)a[i]->theta, W[i].frag, (float*)W[i].bias, st), "pack launch");
+    else
+      HIP_TRY(launch_pack_f64(md, G.T, (const double*)a[i]->theta, W[i].frag, (double*)W[i].bias, st), "pack launch");
+    HIP_TRY(launch_prep(h->sys, x[i], B[i], W[i].ediag, W[i].F, st), "prep launch");
+    RowsArgs R{};
+    R.sys = h->sys; R.made = md; R.x = x[i]; R.B = B[i]; R.lpx = W[i].lpx; R.lpx64 = W[i].lpx64;
+    R.zphi = W[i].zphi; R.logpsi = logpsi ? logpsi[i] : nullptr;
+    if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, st), "sample pass launch");
+    else HIP_TRY(launch_rows_f64(R, G.hmax, st), "sample pass launch");
+  }
+  // kernel arguments of every system, in item-space order, and the item prefix
+  for (int k = 0; k < n_sys; ++k) {
+    const int i = M.order[k];
+    const elocal_ctx* h = hs[i];
+    EvalArgs E{};
+    E.sys = h->sys; E.made = M.G[i].md; E.made.wfrag = W[i].frag; E.made.bias = W[i].bias;
+    E.x = x[i]; E.B = B[i]; E.ediag = W[i].ediag; E.F = W[i].F; E.lpx = W[i].lpx; E.lpx64 = W[i].lpx64;
+    E.zphi = W[i].zphi; E.partial = W[i].partial; E.n_items = M.p[i].n_items; E.ips = M.p[i].ips;
+    E.tpi = M.p[i].tpi; E.lds_bias_off = 0; E.lds_ctx_off = 0;
+    HIP_TRY(launch_store_bytes(&E, sizeof(EvalArgs), (char*)d_args + kArgsStride * k, st), "argument store");
+  }
+  HIP_TRY(launch_store_bytes(M.first, sizeof(int64_t) * (n_sys + 1), d_first, st), "argument store");
+  elocal_ctx* h0 = hs[0];
+  const bool timed = h0->timing && M.first[n_sys] > 0;
+  const int slot = (int)(h0->ring_pos % elocal_ctx::kRing);
+  if (M.first[n_sys] > 0) {
+    if (timed) HIP_TRY(hipEventRecord(h0->ev_start[slot], st), "timing event");
+    if (M.precision == ELOCAL_BF16)
+      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.ldsw, M.lds, M.bias_off, M.ctx_off, M.grid, st),
+              "multi eval launch");
+    else
+      HIP_TRY(launch_eval_multi_f64(d_args, d_first, n_sys, M.hmax, M.grid, st), "multi eval launch");
+    if (timed) {
+      HIP_TRY(hipEventRecord(h0->ev_stop[slot], st), "timing event");
+      h0->ring_pos++;
+      h0->recorded++;
+    }
+  }
+  for (int i = 0; i < n_sys; ++i)
+    if (B[i] > 0) HIP_TRY(launch_reduce(W[i].ediag, W[i].partial, B[i], M.p[i].ips, eloc[i], st), "reduce launch");
   return ELOCAL_OK;
 }
 

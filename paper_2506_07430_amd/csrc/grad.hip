@@ -3,6 +3,8 @@
 // Every reduction runs in a fixed order (no floating-point atomics), so results are
 // bitwise repeatable.
 #include "elocal_internal.hpp"
+#include <cstring>
+
 #include "kernels.hpp"
 
 namespace elocal {
@@ -255,7 +257,36 @@ __global__ void k_write_dtheta(GradPlan G) {
   }
 }
 
+// Copies a small host-side record (passed by value) to device memory, so a call can
+// hand per-system descriptors to a kernel without a host buffer or a synchronisation.
+struct Words256 {
+  uint32_t w[256];
+};
+
+__global__ void k_store_words(Words256 src, uint32_t count, uint32_t* __restrict__ dst) {
+  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src.w[i];
+}
+
 // ----------------------------------------------------------------------------- launchers
+hipError_t launch_store_bytes(const void* src, size_t bytes, void* dst, hipStream_t st) {
+  if (bytes % 4) return hipErrorInvalidValue;
+  const uint32_t* s = (const uint32_t*)src;
+  uint32_t* d = (uint32_t*)dst;
+  size_t words = bytes / 4;
+  while (words > 0) {
+    const uint32_t cnt = (uint32_t)(words < 256 ? words : 256);
+    Words256 w;
+    std::memcpy(w.w, s, cnt * 4);
+    hipLaunchKernelGGL(k_store_words, dim3(1), dim3(256), 0, st, w, cnt, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    s += cnt;
+    d += cnt;
+    words -= cnt;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_reduce(const double* ediag, const double* partial, int64_t B, uint32_t ips,
                          double* eloc, hipStream_t st) {
   if (B <= 0) return hipSuccess;

@@ -60,6 +60,21 @@ hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, hipStream_t st);
 hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, bool lds_weights, size_t lds_bytes,
                             unsigned grid, hipStream_t st);
 
+// Waves per block of the BF16 fused kernels (single and multi-system), one block per CU:
+// two waves per SIMD up to hidden width 128, one (with 512 registers) at width 256.
+constexpr int eval_waves_bf16(int hmax) { return hmax <= 128 ? 8 : 4; }
+constexpr int kMaxEvalWavesBF16 = 8;
+// Several systems in one launch: args[s] describes system s (device copy). BF16: system
+// s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax) work items each (LDS layout as
+// for one system: weights at 0, biases at bias_off, wave contexts at ctx_off). FP64:
+// system s owns work items [first[s], first[s+1]).
+hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, bool ldsw,
+                                  size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st);
+hipError_t launch_eval_multi_f64(const EvalArgs* args, const int64_t* first, int n_sys, int hmax,
+                                 unsigned grid, hipStream_t st);
+// Host record (bytes a multiple of 4) -> device memory, in stream order.
+hipError_t launch_store_bytes(const void* src, size_t bytes, void* dst, hipStream_t st);
+
 hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta,
                            void* frag, double* bias, hipStream_t st);
 hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st);

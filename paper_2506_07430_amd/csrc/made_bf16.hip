@@ -390,130 +390,203 @@ struct WaveCtxBF16 {
   float lpx[kMaxOrb];   // log2 p_p(s_p) of the sample
 };
 
+// What a wave keeps of the sample its current work item belongs to.
+template <int NW>
+struct SampleState {
+  int64_t b;
+  uint64_t xs[NW];
+  double sig_x, ed;
+  const double* Fs;
+};
+
 // One work item = one sample and P.tpi consecutive groups of 64 list entries. Per group:
 // every lane generates one entry (x', H_{x'x} in FP64, first changed orbital); the
 // network runs twice on 32 of them; every lane then forms H exp(dA + i dphi) in FP64
-// for its own entry. Partial sums are per item, in a fixed order.
-template <int HMAX, int NW, bool LDSW>
-__global__ void __launch_bounds__(256, (HMAX <= 128 ? 2 : 1)) k_eval_bf16(EvalArgs P) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+// for its own entry. The item's partial sum (fixed order) goes to P.partial[item].
+template <int HMAX, int NW>
+__device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* __restrict__ W,
+                                               const float* __restrict__ bias, WaveCtxBF16& wc,
+                                               int64_t item, SampleState<NW>& st, int lane) {
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
-  const bf16x8* W = (const bf16x8*)M.wfrag;
-  const float* bias = (const float*)M.bias;
-  if (LDSW) {
-    bf16x8* sw = (bf16x8*)smem;
-    const bf16x8* gw = (const bf16x8*)M.wfrag;
-    for (uint32_t i = threadIdx.x; i < M.nfrag * 64u; i += blockDim.x) sw[i] = gw[i];
-    float* sb = (float*)(smem + P.lds_bias_off);
-    for (uint32_t i = threadIdx.x; i < M.nbias; i += blockDim.x) sb[i] = bias[i];
-    __syncthreads();
-    W = sw;
-    bias = sb;
-  }
-  WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + P.lds_ctx_off))[wid];
+  const int g = lane >> 4, r16 = lane & 15;
   const int n = S.n, na = S.na, nb = S.nb;
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
-  const uint32_t nS = S.nSa + S.nSb;
-  int64_t cur_b = -1;
-  uint64_t xs[NW];
-  double sig_x = 0.0, ed = 0.0;
-  const double* Fs = P.F;
-  for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < P.n_items; item += (int64_t)gridDim.x * 4) {
-    const int64_t b = item / P.ips;
-    const uint32_t seg = (uint32_t)(item % P.ips);
-    if (b != cur_b) {
-      wave_sync_lds();
+  const int64_t b = item / P.ips;
+  const uint32_t seg = (uint32_t)(item % P.ips);
+  if (b != st.b) {
+    wave_sync_lds();
 #pragma unroll
-      for (int w = 0; w < NW; ++w) xs[w] = P.x[b * NW + w];
-      build_ctx<NW>(S, xs, wc.c, lane);
-      if (lane < n) wc.lpx[lane] = P.lpx[b * n + lane];
-      wave_sync_lds();
-      sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
-      ed = P.ediag[b];
-      Fs = P.F + (size_t)b * nS;
-      cur_b = b;
+    for (int w = 0; w < NW; ++w) st.xs[w] = P.x[b * NW + w];
+    build_ctx<NW>(S, st.xs, wc.c, lane);
+    if (lane < n) wc.lpx[lane] = P.lpx[b * n + lane];
+    wave_sync_lds();
+    st.sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
+    st.ed = P.ediag[b];
+    st.Fs = P.F + (size_t)b * (S.nSa + S.nSb);
+    st.b = b;
+  }
+  const uint64_t(&xs)[NW] = st.xs;
+  double acc_re = 0.0, acc_im = 0.0;
+  for (uint32_t grp = 0; grp < P.tpi; ++grp) {
+    const uint32_t t0 = 1u + (seg * P.tpi + grp) * 64u;
+    if (t0 >= S.C) break;
+    // ---- generate this lane's entry
+    const uint32_t t = t0 + lane;
+    uint64_t xo[NW];
+    double hv = 0.0;
+    if (t < S.C) {
+      const Excitation e = unrank(S, wc.c, t);
+      const int sg = apply_excitation<NW>(xs, e, xo);
+      const double v = excitation_value(S, e, st.Fs, st.ed);
+      hv = sg < 0 ? -v : v;
+    } else {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) xo[w] = xs[w];
     }
-    double acc_re = 0.0, acc_im = 0.0;
-    for (uint32_t grp = 0; grp < P.tpi; ++grp) {
-      const uint32_t t0 = 1u + (seg * P.tpi + grp) * 64u;
-      if (t0 >= S.C) break;
-      // ---- generate this lane's entry
-      const uint32_t t = t0 + lane;
-      uint64_t xo[NW];
-      double hv = 0.0;
-      if (t < S.C) {
-        const Excitation e = unrank(S, wc.c, t);
-        const int sg = apply_excitation<NW>(xs, e, xo);
-        const double v = excitation_value(S, e, Fs, ed);
-        hv = sg < 0 ? -v : v;
-      } else {
+    const int p0o = first_diff_orbital<NW>(xs, xo, n);
+    const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
+    double dA_own = 0.0;
+    float zp_own = 0.f;
+    // ---- network on entries 32h .. 32h + 31
 #pragma unroll
-        for (int w = 0; w < NW; ++w) xo[w] = xs[w];
+    for (int h = 0; h < 2; ++h) {
+      uint64_t xr[2][NW];
+      int p0[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int src = 32 * h + 16 * c + r16;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xr[c][w] = __shfl(xo[w], src);
+        p0[c] = __shfl(p0o, src);
       }
-      const int p0o = first_diff_orbital<NW>(xs, xo, n);
-      const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
-      double dA_own = 0.0;
-      float zp_own = 0.f;
-      // ---- network on entries 32h .. 32h + 31
+      double dA[2] = {0.0, 0.0};
+      float zp[2] = {0.f, 0.f};
+      const int pfirst = 4 * ob_first + g;
+      RowCounts rc[2] = {counts_before<NW>(xr[0], pfirst), counts_before<NW>(xr[1], pfirst)};
+      mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
+        const int p = 4 * ob + g;
+        if (p < n) {
+          const float lx = wc.lpx[p];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint64_t xr[2][NW];
-        int p0[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int src = 32 * h + 16 * c + r16;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) xr[c][w] = __shfl(xo[w], src);
-          p0[c] = __shfl(p0o, src);
-        }
-        double dA[2] = {0.0, 0.0};
-        float zp[2] = {0.f, 0.f};
-        const int pfirst = 4 * ob_first + g;
-        RowCounts rc[2] = {counts_before<NW>(xr[0], pfirst), counts_before<NW>(xr[1], pfirst)};
-        mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
-          const int p = 4 * ob + g;
-          if (p < n) {
-            const float lx = wc.lpx[p];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const float lp = cond_log2p_step<NW>(xr[c], p, n, na, nb, c ? a1 : a0, rc[c]);
-              dA[c] += (double)(p >= p0[c] ? lp - lx : 0.f);
-            }
+          for (int c = 0; c < 2; ++c) {
+            const float lp = cond_log2p_step<NW>(xr[c], p, n, na, nb, c ? a1 : a0, rc[c]);
+            dA[c] += (double)(p >= p0[c] ? lp - lx : 0.f);
           }
-          if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
-        });
+        }
+        if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
+      });
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          dA[c] += __shfl_xor(dA[c], 16);
-          dA[c] += __shfl_xor(dA[c], 32);
-          zp[c] = __shfl(zp[c], g_phi * 16 + r16);
-        }
-        if ((lane >> 5) == h) {
-          const int c = (lane >> 4) & 1;
-          dA_own = c ? dA[1] : dA[0];
-          zp_own = c ? zp[1] : zp[0];
-        }
+      for (int c = 0; c < 2; ++c) {
+        dA[c] += __shfl_xor(dA[c], 16);
+        dA[c] += __shfl_xor(dA[c], 32);
+        zp[c] = __shfl(zp[c], g_phi * 16 + r16);
       }
-      // ---- FP64 ratio and accumulation, one entry per lane
-      if (t < S.C) {
-        const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-(double)zp_own)) - sig_x);
-        double sn, cs;
-        sincos(dphi, &sn, &cs);
-        const double mag = hv * exp((0.5 * kLn2) * dA_own);
-        acc_re += mag * cs;
-        acc_im += mag * sn;
+      if ((lane >> 5) == h) {
+        const int c = (lane >> 4) & 1;
+        dA_own = c ? dA[1] : dA[0];
+        zp_own = c ? zp[1] : zp[0];
       }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      acc_re += __shfl_xor(acc_re, off);
-      acc_im += __shfl_xor(acc_im, off);
+    // ---- FP64 ratio and accumulation, one entry per lane
+    if (t < S.C) {
+      const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-(double)zp_own)) - st.sig_x);
+      double sn, cs;
+      sincos(dphi, &sn, &cs);
+      const double mag = hv * exp((0.5 * kLn2) * dA_own);
+      acc_re += mag * cs;
+      acc_im += mag * sn;
     }
-    if (lane == 0) {
-      P.partial[2 * item] = acc_re;
-      P.partial[2 * item + 1] = acc_im;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    acc_re += __shfl_xor(acc_re, off);
+    acc_im += __shfl_xor(acc_im, off);
+  }
+  if (lane == 0) {
+    P.partial[2 * item] = acc_re;
+    P.partial[2 * item + 1] = acc_im;
+  }
+}
+
+// Block shape of the fused kernels: one block per CU, so the whole 160 KiB of LDS can
+// hold the packed weights of one ansatz; 8 waves (two per SIMD) up to width 128.
+
+__device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* smem, uint32_t bias_off) {
+  bf16x8* sw = (bf16x8*)smem;
+  const bf16x8* gw = (const bf16x8*)M.wfrag;
+  for (uint32_t i = threadIdx.x; i < M.nfrag * 64u; i += blockDim.x) sw[i] = gw[i];
+  float* sb = (float*)(smem + bias_off);
+  const float* gb = (const float*)M.bias;
+  for (uint32_t i = threadIdx.x; i < M.nbias; i += blockDim.x) sb[i] = gb[i];
+}
+
+// One system; a persistent grid strides over the work items, one wave per item. With
+// LDSW the packed weights and biases are first staged in LDS.
+template <int HMAX, int NW, bool LDSW>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1) k_eval_bf16(EvalArgs P) {
+  constexpr int kEvalWaves = eval_waves_bf16(HMAX);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
+  const bf16x8* W = (const bf16x8*)P.made.wfrag;
+  const float* bias = (const float*)P.made.bias;
+  if (LDSW) {
+    stage_weights(P.made, smem, P.lds_bias_off);
+    __syncthreads();
+    W = (const bf16x8*)smem;
+    bias = (const float*)(smem + P.lds_bias_off);
+  }
+  WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + P.lds_ctx_off))[wid];
+  SampleState<NW> st;
+  st.b = -1;
+  for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
+       item += (int64_t)gridDim.x * kEvalWaves)
+    eval_item_bf16<HMAX, NW>(P, W, bias, wc, item, st, lane);
+}
+
+// Several systems in one persistent launch. Work is cut into chunks of kEvalWaves items
+// (one per wave of a block) that never straddle two systems; system s owns chunks
+// [first[s], first[s+1]). Blocks stride over the chunks, so every block's share mixes
+// the systems in proportion and no system leaves a tail of its own. With LDSW a block
+// restages the weights whenever its next chunk belongs to another system.
+template <int HMAX, bool LDSW>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1)
+    k_eval_multi_bf16(const EvalArgs* __restrict__ args, const int64_t* __restrict__ first, int n_sys,
+                      uint32_t lds_bias_off, uint32_t lds_ctx_off) {
+  constexpr int kEvalWaves = eval_waves_bf16(HMAX);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
+  WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + lds_ctx_off))[wid];
+  SampleState<1> st1;
+  SampleState<2> st2;
+  st1.b = st2.b = -1;
+  int cur = -1;
+  const bf16x8* W = nullptr;
+  const float* bias = nullptr;
+  const int64_t chunks = first[n_sys];
+  for (int64_t chunk = blockIdx.x; chunk < chunks; chunk += gridDim.x) {
+    int s = 0;
+    while (s + 1 < n_sys && chunk >= first[s + 1]) ++s;
+    s = sgpr(s);
+    const EvalArgs& P = args[s];
+    if (s != cur) {
+      cur = s;
+      st1.b = st2.b = -1;
+      if (LDSW) {
+        __syncthreads();   // every wave is done with the previous system's weights
+        stage_weights(P.made, smem, lds_bias_off);
+        __syncthreads();
+        W = (const bf16x8*)smem;
+        bias = (const float*)(smem + lds_bias_off);
+      } else {
+        W = (const bf16x8*)P.made.wfrag;
+        bias = (const float*)P.made.bias;
+      }
+    }
+    const int64_t local = (chunk - first[s]) * kEvalWaves + wid;
+    if (local < P.n_items) {
+      if (P.sys.W == 1) eval_item_bf16<HMAX, 1>(P, W, bias, wc, local, st1, lane);
+      else eval_item_bf16<HMAX, 2>(P, W, bias, wc, local, st2, lane);
     }
   }
 }
@@ -554,7 +627,7 @@ static hipError_t eval_bf16_k(const EvalArgs& A, size_t lds, unsigned grid, hipS
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, A);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX)), lds, st, A);
   return hipGetLastError();
 }
 
@@ -563,6 +636,36 @@ static hipError_t eval_bf16_h(const EvalArgs& A, bool ldsw, size_t lds, unsigned
   if (A.sys.W == 1)
     return ldsw ? eval_bf16_k<HMAX, 1, true>(A, lds, grid, st) : eval_bf16_k<HMAX, 1, false>(A, lds, grid, st);
   return ldsw ? eval_bf16_k<HMAX, 2, true>(A, lds, grid, st) : eval_bf16_k<HMAX, 2, false>(A, lds, grid, st);
+}
+
+template <int HMAX, bool LDSW>
+static hipError_t eval_multi_bf16_k(const EvalArgs* args, const int64_t* first, int n_sys, size_t lds,
+                                    uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st) {
+  auto kern = k_eval_multi_bf16<HMAX, LDSW>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX)), lds, st, args, first, n_sys, bias_off, ctx_off);
+  return hipGetLastError();
+}
+
+template <int HMAX>
+static hipError_t eval_multi_bf16_h(const EvalArgs* args, const int64_t* first, int n_sys, bool ldsw, size_t lds,
+                                    uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st) {
+  return ldsw ? eval_multi_bf16_k<HMAX, true>(args, first, n_sys, lds, bias_off, ctx_off, grid, st)
+              : eval_multi_bf16_k<HMAX, false>(args, first, n_sys, lds, bias_off, ctx_off, grid, st);
+}
+
+hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, bool ldsw,
+                                  size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st) {
+  switch (hmax) {
+    case 32: return eval_multi_bf16_h<32>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
+    case 64: return eval_multi_bf16_h<64>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
+    case 128: return eval_multi_bf16_h<128>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
+    case 256: return eval_multi_bf16_h<256>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, bool ldsw, size_t lds, unsigned grid,

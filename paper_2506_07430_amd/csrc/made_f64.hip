@@ -192,83 +192,122 @@ struct WaveCtx64 {
   double lpx[kMaxOrb];
 };
 
+template <int NW>
+struct SampleState64 {
+  int64_t b;
+  uint64_t xs[NW];
+  double sig_x, ed;
+  const double* Fs;
+};
+
+// One work item = one sample and P.tpi tiles of 16 list entries; the 64 lanes of a tile
+// share its 16 rows (lane group g holds output units 4g..4g+3 of each 16-unit block).
 template <int HMAX, int NW>
-__global__ void __launch_bounds__(256) k_eval_f64(EvalArgs P) {
-  __shared__ WaveCtx64 ctxs[4];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+__device__ __forceinline__ void eval_item_f64(const EvalArgs& P, WaveCtx64& wc, int64_t item,
+                                              SampleState64<NW>& st, int lane) {
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
   const double* W = (const double*)M.wfrag;
   const double* bias = (const double*)M.bias;
-  WaveCtx64& wc = ctxs[wid];
+  const int g = lane >> 4, r16 = lane & 15;
   const int n = S.n, na = S.na, nb = S.nb;
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
-  const uint32_t nS = S.nSa + S.nSb;
-  int64_t cur_b = -1;
-  uint64_t xs[NW];
-  double sig_x = 0.0, ed = 0.0;
-  const double* Fs = P.F;
-  for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < P.n_items; item += (int64_t)gridDim.x * 4) {
-    const int64_t b = item / P.ips;
-    const uint32_t seg = (uint32_t)(item % P.ips);
-    if (b != cur_b) {
-      wave_sync_lds64();
+  const int64_t b = item / P.ips;
+  const uint32_t seg = (uint32_t)(item % P.ips);
+  if (b != st.b) {
+    wave_sync_lds64();
 #pragma unroll
-      for (int w = 0; w < NW; ++w) xs[w] = P.x[b * NW + w];
-      build_ctx<NW>(S, xs, wc.c, lane);
-      if (lane < n) wc.lpx[lane] = P.lpx64[b * n + lane];
-      wave_sync_lds64();
-      sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
-      ed = P.ediag[b];
-      Fs = P.F + (size_t)b * nS;
-      cur_b = b;
-    }
-    double acc_re = 0.0, acc_im = 0.0;
-    for (uint32_t tile = 0; tile < P.tpi; ++tile) {
-      const uint32_t t0 = 1u + (seg * P.tpi + tile) * 16u;
-      if (t0 >= S.C) break;
-      const uint32_t t = t0 + r16;
-      uint64_t xp[NW];
-      double hv = 0.0;
-      if (t < S.C) {
-        const Excitation e = unrank(S, wc.c, t);
-        const int sg = apply_excitation<NW>(xs, e, xp);
-        if (g == 0) {
-          const double v = excitation_value(S, e, Fs, ed);
-          hv = sg < 0 ? -v : v;
-        }
-      } else {
-#pragma unroll
-        for (int w = 0; w < NW; ++w) xp[w] = xs[w];
-      }
-      const int p0 = first_diff_orbital<NW>(xs, xp, n);
-      double dA = 0.0, zp = 0.0;
-      mlp_f64<HMAX, NW>(M, W, bias, xp, lane, [&](int ob, const f64x4& a) {
-        const int p = 4 * ob + g;
-        if (p < n && p >= p0) dA += cond_logp64<NW>(xp, p, n, na, nb, a) - wc.lpx[p];
-        if (ob == ob_phi && g == g_phi) zp = a[0];
-      });
-      dA += __shfl_xor(dA, 16);
-      dA += __shfl_xor(dA, 32);
-      zp = __shfl(zp, g_phi * 16 + r16);
+    for (int w = 0; w < NW; ++w) st.xs[w] = P.x[b * NW + w];
+    build_ctx<NW>(S, st.xs, wc.c, lane);
+    if (lane < n) wc.lpx[lane] = P.lpx64[b * n + lane];
+    wave_sync_lds64();
+    st.sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
+    st.ed = P.ediag[b];
+    st.Fs = P.F + (size_t)b * (S.nSa + S.nSb);
+    st.b = b;
+  }
+  const uint64_t(&xs)[NW] = st.xs;
+  double acc_re = 0.0, acc_im = 0.0;
+  for (uint32_t tile = 0; tile < P.tpi; ++tile) {
+    const uint32_t t0 = 1u + (seg * P.tpi + tile) * 16u;
+    if (t0 >= S.C) break;
+    const uint32_t t = t0 + r16;
+    uint64_t xp[NW];
+    double hv = 0.0;
+    if (t < S.C) {
+      const Excitation e = unrank(S, wc.c, t);
+      const int sg = apply_excitation<NW>(xs, e, xp);
       if (g == 0) {
-        const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-zp)) - sig_x);
-        double sn, cs;
-        sincos(dphi, &sn, &cs);
-        const double mag = hv * exp(0.5 * dA);
-        acc_re += mag * cs;
-        acc_im += mag * sn;
+        const double v = excitation_value(S, e, st.Fs, st.ed);
+        hv = sg < 0 ? -v : v;
       }
-    }
+    } else {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      acc_re += __shfl_xor(acc_re, off);
-      acc_im += __shfl_xor(acc_im, off);
+      for (int w = 0; w < NW; ++w) xp[w] = xs[w];
     }
-    if (lane == 0) {
-      P.partial[2 * item] = acc_re;
-      P.partial[2 * item + 1] = acc_im;
+    const int p0 = first_diff_orbital<NW>(xs, xp, n);
+    double dA = 0.0, zp = 0.0;
+    mlp_f64<HMAX, NW>(M, W, bias, xp, lane, [&](int ob, const f64x4& a) {
+      const int p = 4 * ob + g;
+      if (p < n && p >= p0) dA += cond_logp64<NW>(xp, p, n, na, nb, a) - wc.lpx[p];
+      if (ob == ob_phi && g == g_phi) zp = a[0];
+    });
+    dA += __shfl_xor(dA, 16);
+    dA += __shfl_xor(dA, 32);
+    zp = __shfl(zp, g_phi * 16 + r16);
+    if (g == 0) {
+      const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-zp)) - st.sig_x);
+      double sn, cs;
+      sincos(dphi, &sn, &cs);
+      const double mag = hv * exp(0.5 * dA);
+      acc_re += mag * cs;
+      acc_im += mag * sn;
     }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    acc_re += __shfl_xor(acc_re, off);
+    acc_im += __shfl_xor(acc_im, off);
+  }
+  if (lane == 0) {
+    P.partial[2 * item] = acc_re;
+    P.partial[2 * item + 1] = acc_im;
+  }
+}
+
+template <int HMAX, int NW>
+__global__ void __launch_bounds__(256) k_eval_f64(EvalArgs P) {
+  __shared__ WaveCtx64 ctxs[4];
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  SampleState64<NW> st;
+  st.b = -1;
+  for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < P.n_items; item += (int64_t)gridDim.x * 4)
+    eval_item_f64<HMAX, NW>(P, ctxs[wid], item, st, lane);
+}
+
+// Several systems in one persistent launch (item index space as in the BF16 kernel).
+template <int HMAX>
+__global__ void __launch_bounds__(256)
+    k_eval_multi_f64(const EvalArgs* __restrict__ args, const int64_t* __restrict__ first, int n_sys) {
+  __shared__ WaveCtx64 ctxs[4];
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  SampleState64<1> st1;
+  SampleState64<2> st2;
+  st1.b = st2.b = -1;
+  int cur = -1;
+  const int64_t total = first[n_sys];
+  for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < total; item += (int64_t)gridDim.x * 4) {
+    int s = 0;
+    while (s + 1 < n_sys && item >= first[s + 1]) ++s;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s != cur) {
+      st1.b = st2.b = -1;
+      cur = s;
+    }
+    const EvalArgs& P = args[s];
+    const int64_t local = item - first[s];
+    if (P.sys.W == 1) eval_item_f64<HMAX, 1>(P, ctxs[wid], local, st1, lane);
+    else eval_item_f64<HMAX, 2>(P, ctxs[wid], local, st2, lane);
   }
 }
 
@@ -305,6 +344,24 @@ static hipError_t eval_f64_h(const EvalArgs& A, unsigned grid, hipStream_t st) {
   if (A.sys.W == 1) hipLaunchKernelGGL((k_eval_f64<HMAX, 1>), dim3(grid), dim3(256), 0, st, A);
   else hipLaunchKernelGGL((k_eval_f64<HMAX, 2>), dim3(grid), dim3(256), 0, st, A);
   return hipGetLastError();
+}
+
+template <int HMAX>
+static hipError_t eval_multi_f64_h(const EvalArgs* args, const int64_t* first, int n_sys, unsigned grid,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(k_eval_multi_f64<HMAX>, dim3(grid), dim3(256), 0, st, args, first, n_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_multi_f64(const EvalArgs* args, const int64_t* first, int n_sys, int hmax,
+                                 unsigned grid, hipStream_t st) {
+  switch (hmax) {
+    case 32: return eval_multi_f64_h<32>(args, first, n_sys, grid, st);
+    case 64: return eval_multi_f64_h<64>(args, first, n_sys, grid, st);
+    case 128: return eval_multi_f64_h<128>(args, first, n_sys, grid, st);
+    case 256: return eval_multi_f64_h<256>(args, first, n_sys, grid, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream_t st) {

@@ -66,8 +66,12 @@ def lib():
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
         L.elocal_tune.argtypes = [vp, i32, i64]
+        L.elocal_workspace_bytes_multi.argtypes = [i32, P(vp), P(P(_Ansatz)), P(i64)]
+        L.elocal_workspace_bytes_multi.restype = sz
+        L.elocal_eval_multi.argtypes = [i32, P(vp), vp, P(P(_Ansatz)), P(vp), P(i64), vp, sz, P(vp), P(vp)]
         for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
-                  "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune"):
+                  "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune",
+                  "elocal_eval_multi"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -76,7 +80,8 @@ def lib():
 def exported_symbols() -> Sequence[str]:
     return ["elocal_create", "elocal_destroy", "elocal_num_connected", "elocal_words", "elocal_num_params",
             "elocal_workspace_bytes", "elocal_connect", "elocal_eval", "elocal_stats", "elocal_grad",
-            "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune", "elocal_last_error"]
+            "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune", "elocal_last_error",
+            "elocal_workspace_bytes_multi", "elocal_eval_multi"]
 
 
 def _check(status: int):
@@ -236,6 +241,60 @@ class Hamiltonian:
         if st not in (0, 2):
             _check(st)
         return int(bad.value)
+
+
+MAX_SYSTEMS = 16
+
+
+class MultiEval:
+    """Local energies of several systems in one persistent launch (elocal_eval_multi).
+
+    Holds the workspace between calls; every system keeps its own Hamiltonian handle,
+    ansatz and samples.
+    """
+
+    def __init__(self):
+        self._ws = None
+
+    @staticmethod
+    def _arrays(hams: Sequence[Hamiltonian], ansatze: Sequence[Ansatz], xs: Sequence[torch.Tensor]):
+        k = len(hams)
+        if not (1 <= k <= MAX_SYSTEMS) or len(ansatze) != k or len(xs) != k:
+            raise ElocalError(1, f"need 1..{MAX_SYSTEMS} systems with one ansatz and one x each")
+        hs = (ctypes.c_void_p * k)(*[h._h for h in hams])
+        for a in ansatze:
+            a.ref()   # refresh the theta pointer
+        ap = (ctypes.POINTER(_Ansatz) * k)(*[ctypes.pointer(a._s) for a in ansatze])
+        xs = [h._x(x) for h, x in zip(hams, xs)]
+        B = (ctypes.c_int64 * k)(*[x.shape[0] for x in xs])
+        return k, hs, ap, xs, B
+
+    def workspace_bytes(self, hams, ansatze, xs) -> int:
+        k, hs, ap, xs, B = self._arrays(hams, ansatze, xs)
+        n = lib().elocal_workspace_bytes_multi(k, hs, ap, B)
+        if n == 0:
+            raise ElocalError(1, lib().elocal_last_error().decode())
+        return int(n)
+
+    def __call__(self, hams: Sequence[Hamiltonian], ansatze: Sequence[Ansatz], xs: Sequence[torch.Tensor],
+                 outs: Optional[Sequence[torch.Tensor]] = None, want_logpsi: bool = False, stream=None):
+        """([eloc_s [B_s, 2]], [logpsi_s [B_s, 2]] or None)."""
+        k, hs, ap, xs, B = self._arrays(hams, ansatze, xs)
+        need = lib().elocal_workspace_bytes_multi(k, hs, ap, B)
+        if need == 0:
+            raise ElocalError(1, lib().elocal_last_error().decode())
+        dev = xs[0].device
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        if outs is None:
+            outs = [torch.empty((x.shape[0], 2), dtype=torch.float64, device=dev) for x in xs]
+        lps = [torch.empty((x.shape[0], 2), dtype=torch.float64, device=dev) for x in xs] if want_logpsi else None
+        xp = (ctypes.c_void_p * k)(*[x.data_ptr() for x in xs])
+        ep = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+        lp = (ctypes.c_void_p * k)(*[t.data_ptr() for t in lps]) if lps is not None else None
+        _check(lib().elocal_eval_multi(k, hs, _stream(stream), ap, xp, B, self._ws.data_ptr(), self._ws.numel(),
+                                       ep, lp))
+        return list(outs), lps
 
 
 def stats(eloc: torch.Tensor, w: torch.Tensor, stream=None) -> torch.Tensor:

@@ -1,0 +1,83 @@
+"""Several systems in one persistent launch (elocal_eval_multi) on the GPU.
+
+The multi-system call must give every system exactly (bitwise) what the single-system
+call gives it: the per-sample work and its summation order are the same, only the
+scheduling of work items over the grid differs. Values are also checked against the
+FP64 oracle (BF16 mode within 1e-5 Ha on the same BF16-rounded parameters; FP64 mode
+within 1e-8 relative). The systems are those of the eight-system workload (n = 12..40
+at half filling, two hidden layers of 128; n = 36 and 40 need two words per
+determinant), with reduced sample counts, an empty batch and a single sample.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import energy as oen
+from paper_2506_07430_amd import elocal, synth
+from tests.gpu_common import make_ham, theta_for, words_to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    torch.cuda.set_device(0)
+
+
+def _c(e):
+    e = e.cpu().numpy()
+    return e[:, 0] + 1j * e[:, 1]
+
+
+def _setup(counts, precision):
+    probs, hams, ans, xs = [], [], [], []
+    for si, cnt in enumerate(counts):
+        p = synth.make_problem(2, si, samples=max(cnt, 1))
+        x = p.x[:cnt]
+        th_dev, th_or = theta_for(p.theta, precision)
+        probs.append((p, x, th_or))
+        hams.append(make_ham(p))
+        ans.append(elocal.Ansatz(p.system.widths, th_dev, precision))
+        xs.append(words_to_dev(x) if cnt > 0 else torch.empty((0, hams[-1].W), dtype=torch.int64, device="cuda"))
+    return probs, hams, ans, xs
+
+
+@pytest.mark.parametrize("precision,counts,oracle_systems", [
+    (elocal.BF16, [24, 0, 17, 1, 9, 16, 5, 12], (0, 2, 3)),
+    (elocal.FP64, [3, 2, 0, 1, 2, 1, 1, 2], (0, 3)),
+])
+def test_multi_equals_single_and_oracle(precision, counts, oracle_systems):
+    probs, hams, ans, xs = _setup(counts, precision)
+    print(f"multi: precision {precision}, counts {counts}", flush=True)
+    multi, lps = elocal.MultiEval()(hams, ans, xs, want_logpsi=True)
+    torch.cuda.synchronize()
+    for si, (h, a, x) in enumerate(zip(hams, ans, xs)):
+        if x.shape[0] == 0:
+            assert multi[si].shape == (0, 2)
+            continue
+        single, lp1 = h.eval(a, x)
+        torch.cuda.synchronize()
+        assert torch.equal(multi[si], single), f"system {si}: multi-system result differs from single"
+        assert torch.equal(lps[si], lp1)
+    for si in oracle_systems:
+        p, x, th = probs[si]
+        k = min(2, x.shape[0])
+        s = p.system
+        ref = oen.local_energies(p.h1e, p.eri, s.n, s.n_alpha, s.n_beta, s.widths, th, x[:k])
+        got = _c(multi[si])[:k]
+        if precision == elocal.BF16:
+            assert np.max(np.abs(got - ref)) <= 1e-5
+        else:
+            assert np.all(np.abs(got - ref) <= 1e-8 * np.abs(ref))
+
+
+def test_multi_rejects_mixed_precision_and_bad_counts():
+    probs, hams, ans, xs = _setup([2, 2], elocal.BF16)
+    p, _, _ = probs[1]
+    th64, _ = theta_for(p.theta, elocal.FP64)
+    mixed = [ans[0], elocal.Ansatz(p.system.widths, th64, elocal.FP64)]
+    with pytest.raises(elocal.ElocalError):
+        elocal.MultiEval()(hams, mixed, xs)
+    with pytest.raises(elocal.ElocalError):
+        elocal.MultiEval()(hams * 9, ans * 9, xs * 9)   # 18 > 16 systems
