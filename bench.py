@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of replays of the captured step")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shape")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size reference "
                          "for HBM byte counters)")
@@ -75,7 +78,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2506_07430_amd import elocal, synth
+    from paper_2506_07430_amd import autotune, elocal, synth
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -110,6 +113,7 @@ def main():
         ham.grad(ans, x, w, eloc, stats=stats, dtheta=dth)
 
     def timed(ans, steps, warmup):
+        """Eager launches; also the fused kernel's time from the library's HIP events."""
         for _ in range(warmup):
             step(ans)
         torch.cuda.synchronize()
@@ -124,7 +128,30 @@ def main():
         ham.timing(False)
         return (t1 - t0) / steps, kms / max(nl, 1), nl
 
-    sec16, kern16_ms, nl16 = timed(ans16, args.steps, args.warmup)
+    def timed_graph(ans, steps):
+        """The whole step captured once as a HIP graph, then replayed `steps` times."""
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(ans)                       # workspaces exist before capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step(ans)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tune_table = None
+    if not args.no_autotune:
+        tune_table = autotune.tune_eval(ham, ans16, x)
+    sec16_eager, kern16_ms, nl16 = timed(ans16, args.steps, args.warmup)
+    sec16 = sec16_eager if args.no_graph else timed_graph(ans16, args.steps)
     eloc16 = eloc.cpu().numpy().copy()
     stats16 = stats.cpu().numpy().copy()
     out = {}
@@ -206,6 +233,9 @@ def main():
         "h_elems_per_s": B * C / sec16,
         "energy": {"re": float(stats16[0]), "im": float(stats16[1]), "var": float(stats16[2])},
         "roofline": roof,
+        "timing": {"mode": "eager" if args.no_graph else "hip graph replay", "eager_ms_per_step": sec16_eager * 1e3,
+                   "launch_shape": ({"autotuned": True, "chosen": min(tune_table, key=lambda r: r["ms"]),
+                                     "tried": len(tune_table)} if tune_table else {"autotuned": False})},
     }
     line.update(out)
     print(json.dumps(line), flush=True)

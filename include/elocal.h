@@ -66,10 +66,15 @@ typedef enum {
 
 /* Arithmetic of the ansatz. H_{xx'}, ratios and every sum stay FP64 in both modes. */
 enum {
-  ELOCAL_FP64 = 0,  /* theta is double; ansatz on FP64 matrix cores                      */
-  ELOCAL_BF16 = 1   /* theta is bfloat16 (uint16 bit patterns); ansatz GEMMs on BF16
-                       matrix cores with FP32 accumulation, activations carried as a
-                       hi+lo pair of bfloat16 values                                      */
+  ELOCAL_FP64 = 0,   /* theta is double; ansatz on FP64 matrix cores                     */
+  ELOCAL_BF16 = 1,   /* theta is bfloat16 (uint16 bit patterns); ansatz GEMMs on BF16
+                        matrix cores with FP32 accumulation, each hidden activation
+                        carried as a hi+lo pair of bfloat16 values (~2^-18 relative)      */
+  ELOCAL_BF16X3 = 2  /* as ELOCAL_BF16 with three bfloat16 terms per activation
+                        (~2^-27 relative; 1.5x the matrix-core work after the first
+                        layer). The rounding of the two-term split, summed over a very
+                        long connected list, grows past 1e-5 Ha per local energy around
+                        n = 60 (1.1e6 connected determinants); three terms keep it below */
 };
 
 /* Operations, for elocal_workspace_bytes. */
@@ -102,7 +107,7 @@ typedef void* elocal_stream;   /* a hipStream_t */
 typedef struct {
   int n_hidden;
   const int* widths;   /* host array [n_hidden]                                  */
-  int precision;       /* ELOCAL_FP64 (theta: double) or ELOCAL_BF16 (theta: uint16) */
+  int precision;       /* ELOCAL_FP64 (theta: double), ELOCAL_BF16 or ELOCAL_BF16X3 (uint16) */
   const void* theta;   /* device pointer, P entries                              */
 } elocal_ansatz;
 
@@ -222,8 +227,10 @@ elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launch
 
 /*
  * Launch shape of the fused local-energy kernel (for the autotuner). A value <= 0
- * restores the built-in choice. ELOCAL_TUNE_GRID: blocks of 4 waves (persistent
- * grid-stride loop over work items); ELOCAL_TUNE_GROUPS: list-entry groups per work
+ * restores the built-in choice. ELOCAL_TUNE_GRID: blocks of the persistent grid-stride
+ * loop over work items (a block has 8 waves in BF16 mode up to hidden width 128, 4
+ * otherwise; elocal_eval_multi takes it from its first handle); ELOCAL_TUNE_GROUPS:
+ * list-entry groups per work
  * item (64 entries per group in BF16 mode, 16 in FP64 mode). Results do not depend on
  * the launch shape except through the fixed per-item summation order (rounding only).
  * Mutates the handle: do not overlap with other calls on it.

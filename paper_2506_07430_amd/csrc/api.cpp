@@ -91,7 +91,9 @@ struct AnsatzGeom {
   MadeDev md{};
   ThetaLayout T{};
   int hmax = 0;
-  int precision = 0;
+  int precision = 0;   // storage/arithmetic family: ELOCAL_FP64 or ELOCAL_BF16
+  int mode = 0;        // the caller's precision (ELOCAL_BF16X3 is in the BF16 family)
+  int nterms = 2;      // bf16 terms per hidden activation (BF16 family)
   size_t wbytes = 0, bbytes = 0;
 };
 
@@ -101,8 +103,11 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   if (a->n_hidden < 1 || a->n_hidden > kMaxHidden)
     return fail(ELOCAL_E_UNSUPPORTED, "n_hidden=%d outside [1, %d]", a->n_hidden, kMaxHidden);
   if (!a->widths) return fail(ELOCAL_E_INVALID, "widths is null");
-  if (a->precision != ELOCAL_FP64 && a->precision != ELOCAL_BF16)
-    return fail(ELOCAL_E_INVALID, "precision=%d is neither ELOCAL_FP64 nor ELOCAL_BF16", a->precision);
+  if (a->precision != ELOCAL_FP64 && a->precision != ELOCAL_BF16 && a->precision != ELOCAL_BF16X3)
+    return fail(ELOCAL_E_INVALID, "precision=%d is not ELOCAL_FP64, ELOCAL_BF16 or ELOCAL_BF16X3", a->precision);
+  // BF16 family: bf16 parameters on BF16 matrix cores; the modes differ in the number of
+  // bf16 terms that carry each hidden activation
+  const bool bf = a->precision != ELOCAL_FP64;
   const int L = a->n_hidden;
   int wmax = 0;
   for (int l = 0; l < L; ++l) {
@@ -112,7 +117,9 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
     wmax = std::max(wmax, w);
   }
   G.hmax = wmax <= 32 ? 32 : wmax <= 64 ? 64 : wmax <= 128 ? 128 : 256;
-  G.precision = a->precision;
+  G.precision = bf ? ELOCAL_BF16 : ELOCAL_FP64;
+  G.mode = a->precision;
+  G.nterms = (a->precision == ELOCAL_BF16X3) ? 3 : 2;
   MadeDev& M = G.md;
   M.n = n;
   M.L = L;
@@ -120,7 +127,7 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   for (int l = 0; l <= L; ++l) {
     M.nin[l] = (l == 0) ? 2 * n : a->widths[l - 1];
     M.nout[l] = (l == L) ? 4 * n + 1 : a->widths[l];
-    M.nk[l] = (a->precision == ELOCAL_BF16) ? (M.nin[l] + 31) / 32 : (M.nin[l] + 3) / 4;
+    M.nk[l] = bf ? (M.nin[l] + 31) / 32 : (M.nin[l] + 3) / 4;
     M.nob[l] = (M.nout[l] + 15) / 16;
     M.woff[l] = wo;
     M.boff[l] = bo;
@@ -132,7 +139,7 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   // k-block ranges of the degree-sorted BF16 packing (FP64 packing is unsorted: full range)
   for (int l = 0; l <= L; ++l)
     for (int ob = 0; ob < kMaxOutBlocks; ++ob) M.kend[l][ob] = (uint8_t)M.nk[l];
-  if (a->precision == ELOCAL_BF16) {
+  if (bf) {
     auto deg_at = [&](int width, int u) { return sorted_unit(n, width, u) % (n - 1) + 1; };
     auto count_le = [&](int width, int D) {
       int c = 0;
@@ -155,8 +162,8 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
       }
     }
   }
-  G.wbytes = (size_t)wo * 64 * (a->precision == ELOCAL_BF16 ? 16 : 8);
-  G.bbytes = (size_t)bo * (a->precision == ELOCAL_BF16 ? 4 : 8);
+  G.wbytes = (size_t)wo * 64 * (bf ? 16 : 8);
+  G.bbytes = (size_t)bo * (bf ? 4 : 8);
   // caller's flat layout
   uint32_t off = 0;
   for (int l = 0; l <= L; ++l) {
@@ -208,7 +215,7 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
     const size_t need = align256(G.wbytes) + align256(G.bbytes) + kCtxBytesBF16;
     p.ldsw = need <= kLdsBytes;   // one 8-wave block per CU owns the CU's LDS
     p.lds = p.ldsw ? need : kCtxBytesBF16;
-    p.waves = eval_waves_bf16(G.hmax);
+    p.waves = eval_waves_bf16(G.hmax, G.nterms);
   } else {
     p.ldsw = false;
     p.lds = 0;
@@ -486,7 +493,7 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
   RowsArgs R{};
   R.sys = h->sys; R.made = M; R.x = x; R.B = B; R.lpx = w.lpx; R.lpx64 = w.lpx64; R.zphi = w.zphi;
   R.logpsi = logpsi;
-  if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, st), "sample pass launch");
+  if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, G.nterms, st), "sample pass launch");
   else HIP_TRY(launch_rows_f64(R, G.hmax, st), "sample pass launch");
   EvalArgs E{};
   E.sys = h->sys; E.made = M; E.x = x; E.B = B; E.ediag = w.ediag; E.F = w.F; E.lpx = w.lpx;
@@ -503,7 +510,7 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
       E.lds_bias_off = 0;
       E.lds_ctx_off = 0;
     }
-    HIP_TRY(launch_eval_bf16(E, G.hmax, p.ldsw, p.lds, p.grid, st), "eval launch");
+    HIP_TRY(launch_eval_bf16(E, G.hmax, G.nterms, p.ldsw, p.lds, p.grid, st), "eval launch");
   } else {
     HIP_TRY(launch_eval_f64(E, G.hmax, p.grid, st), "eval launch");
   }
@@ -551,7 +558,7 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
     if (hs[s]->dev != hs[0]->dev) return fail(ELOCAL_E_INVALID, "handles %d and 0 are on different devices", s);
     if (B[s] < 0) return fail(ELOCAL_E_INVALID, "B[%d]=%lld is negative", s, (long long)B[s]);
     if (elocal_status e = make_geom(hs[s], a[s], M.G[s])) return e;
-    if (s > 0 && M.G[s].precision != M.G[0].precision)
+    if (s > 0 && M.G[s].mode != M.G[0].mode)
       return fail(ELOCAL_E_INVALID, "ansatz %d has another precision than ansatz 0", s);
     M.hmax = std::max(M.hmax, M.G[s].hmax);
     M.p[s] = plan_eval(hs[s], M.G[s], B[s]);
@@ -569,7 +576,7 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   std::stable_sort(M.order, M.order + n_sys, [&](int u, int v) { return cost[u] > cost[v]; });
   // BF16: index space of chunks (one item per wave of a block, never two systems in a
   // chunk); FP64: index space of items
-  const int unit = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax) : 1;
+  const int unit = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax, M.G[0].nterms) : 1;
   M.first[0] = 0;
   for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
   size_t wmax = 0, bmax = 0;
@@ -592,7 +599,7 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   M.first_off = off;
   off = align256(off + sizeof(int64_t) * (n_sys + 1));
   M.bytes = off;
-  const int waves = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax) : 4;
+  const int waves = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax, M.G[0].nterms) : 4;
   const int64_t want = (M.precision == ELOCAL_BF16) ? M.first[n_sys] : (M.first[n_sys] + 3) / 4;
   M.grid = (unsigned)std::max<int64_t>(1, std::min(want, grid_cap(hs[0], waves)));
   return ELOCAL_OK;
@@ -640,7 +647,7 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
     RowsArgs R{};
     R.sys = h->sys; R.made = md; R.x = x[i]; R.B = B[i]; R.lpx = W[i].lpx; R.lpx64 = W[i].lpx64;
     R.zphi = W[i].zphi; R.logpsi = logpsi ? logpsi[i] : nullptr;
-    if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, st), "sample pass launch");
+    if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, G.nterms, st), "sample pass launch");
     else HIP_TRY(launch_rows_f64(R, G.hmax, st), "sample pass launch");
   }
   // kernel arguments of every system, in item-space order, and the item prefix
@@ -661,7 +668,8 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
   if (M.first[n_sys] > 0) {
     if (timed) HIP_TRY(hipEventRecord(h0->ev_start[slot], st), "timing event");
     if (M.precision == ELOCAL_BF16)
-      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.ldsw, M.lds, M.bias_off, M.ctx_off, M.grid, st),
+      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.G[0].nterms, M.ldsw, M.lds, M.bias_off, M.ctx_off,
+                                     M.grid, st),
               "multi eval launch");
     else
       HIP_TRY(launch_eval_multi_f64(d_args, d_first, n_sys, M.hmax, M.grid, st), "multi eval launch");

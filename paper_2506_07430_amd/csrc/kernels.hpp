@@ -56,20 +56,22 @@ hipError_t launch_check(const SysDev& S, const uint64_t* x, int64_t B, unsigned 
 // fused evaluation; `hmax` is the padded hidden width class (32, 64, 128, 256).
 hipError_t launch_pack_bf16(const MadeDev& M, const ThetaLayout& T, const uint16_t* theta,
                             void* frag, float* bias, hipStream_t st);
-hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, hipStream_t st);
-hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, bool lds_weights, size_t lds_bytes,
+hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t st);
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, size_t lds_bytes,
                             unsigned grid, hipStream_t st);
 
 // Waves per block of the BF16 fused kernels (single and multi-system), one block per CU:
-// two waves per SIMD up to hidden width 128, one (with 512 registers) at width 256.
-constexpr int eval_waves_bf16(int hmax) { return hmax <= 128 ? 8 : 4; }
+// two waves per SIMD while the activations (nterms bf16 terms of 32 rows x hmax units,
+// this layer's and the next) fit in 256 registers, else one (with 512 registers).
+constexpr int eval_waves_bf16(int hmax, int nterms) { return hmax * nterms <= 256 ? 8 : 4; }
 constexpr int kMaxEvalWavesBF16 = 8;
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system
-// s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax) work items each (LDS layout as
+// s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax, nterms) work items each (LDS layout as
 // for one system: weights at 0, biases at bias_off, wave contexts at ctx_off). FP64:
 // system s owns work items [first[s], first[s+1]).
-hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, bool ldsw,
-                                  size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st);
+hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
+                                  bool ldsw, size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid,
+                                  hipStream_t st);
 hipError_t launch_eval_multi_f64(const EvalArgs* args, const int64_t* first, int n_sys, int hmax,
                                  unsigned grid, hipStream_t st);
 // Host record (bytes a multiple of 4) -> device memory, in stream order.

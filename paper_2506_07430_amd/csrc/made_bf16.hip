@@ -19,6 +19,8 @@
 // and ReLU) is fed as hi = bf16(a) plus lo = bf16(a - hi), two MFMAs per weight
 // fragment, so the representation error is ~2^-16 |a|. Accumulation is FP32; the
 // ratio exp(dA + i dphi), the matrix element and every sum are FP64.
+#include <type_traits>
+
 #include "elocal_internal.hpp"
 #include "kernels.hpp"
 
@@ -97,33 +99,43 @@ __device__ __forceinline__ bf16x8 bits_to_bf16x8(uint32_t v) {
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-// ReLU of a pair, then hi = bf16(a) (one packed convert) and lo = bf16(a - hi); the
-// FP32 value of hi is recovered from its bits, so each element costs four VALU ops.
-__device__ __forceinline__ void split_pair(float u, float v, uint32_t& hi, uint32_t& lo) {
+// ReLU of a pair, then NT bfloat16 terms whose sum represents each value: t[0] =
+// bf16(a), t[1] = bf16(a - t[0]), t[2] = bf16(a - t[0] - t[1]) (one packed convert per
+// term for both values; the FP32 value of a term is recovered from its bits). Two terms
+// leave ~2^-18 |a|, three ~2^-27 |a|.
+template <int NT>
+__device__ __forceinline__ void split_pair(float u, float v, uint32_t (&t)[NT]) {
   u = __int_as_float(max(__float_as_int(u), 0));     // ReLU: negative floats are negative ints
   v = __int_as_float(max(__float_as_int(v), 0));
-  bf16x2 h;
-  h[0] = (__bf16)u;
-  h[1] = (__bf16)v;
-  uint32_t hb;
-  __builtin_memcpy(&hb, &h, 4);
-  const float uh = __uint_as_float(hb << 16), vh = __uint_as_float(hb & 0xFFFF0000u);
-  bf16x2 l;
-  l[0] = (__bf16)(u - uh);
-  l[1] = (__bf16)(v - vh);
-  __builtin_memcpy(&lo, &l, 4);
-  hi = hb;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    bf16x2 h;
+    h[0] = (__bf16)u;
+    h[1] = (__bf16)v;
+    uint32_t hb;
+    __builtin_memcpy(&hb, &h, 4);
+    t[i] = hb;
+    if (i + 1 < NT) {
+      u -= __uint_as_float(hb << 16);
+      v -= __uint_as_float(hb & 0xFFFF0000u);
+    }
+  }
 }
 
-// Units 4g..4g+3 of block a and of block a+1 -> the 8 k-slots of the next layer.
-__device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, bf16x8& hi, bf16x8& lo) {
-  uint32_t h[4], l[4];
-  split_pair(a[0], a[1], h[0], l[0]);
-  split_pair(a[2], a[3], h[1], l[1]);
-  split_pair(b[0], b[1], h[2], l[2]);
-  split_pair(b[2], b[3], h[3], l[3]);
-  __builtin_memcpy(&hi, h, 16);
-  __builtin_memcpy(&lo, l, 16);
+// Units 4g..4g+3 of block a and of block a+1 -> the 8 k-slots of the next layer, as NT
+// bf16 terms.
+template <int NT>
+__device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, bf16x8 (&out)[NT]) {
+  uint32_t t[4][NT];
+  split_pair<NT>(a[0], a[1], t[0]);
+  split_pair<NT>(a[2], a[3], t[1]);
+  split_pair<NT>(b[0], b[1], t[2]);
+  split_pair<NT>(b[2], b[3], t[3]);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const uint32_t w[4] = {t[0][i], t[1][i], t[2][i], t[3][i]};
+    __builtin_memcpy(&out[i], w, 16);
+  }
 }
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -139,10 +151,10 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
 }
 
 // Output block ob of the last layer for both column blocks (rows r and 16 + r).
-template <int KB>
+template <int KB, int NT>
 __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ W,
-                                          const float* __restrict__ bias, const bf16x8 (&chi)[2][KB],
-                                          const bf16x8 (&clo)[2][KB], int ob, int lane, f32x4 (&a)[2]) {
+                                          const float* __restrict__ bias, const bf16x8 (&act)[NT][2][KB],
+                                          int ob, int lane, f32x4 (&a)[2]) {
   const int l = M.L, nk = M.nk[l], ke = sgpr(M.kend[l][ob]);
   a[0] = a[1] = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
   const bf16x8* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
@@ -151,25 +163,25 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __rest
     if (kb < ke) {
       const bf16x8 w = wp[kb * 64];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        a[c] = mfma_bf16(w, chi[c][kb], a[c]);
-        a[c] = mfma_bf16(w, clo[c][kb], a[c]);
-      }
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < NT; ++i) a[c] = mfma_bf16(w, act[i][c][kb], a[c]);
     }
   }
 }
 
 // Runs the network on two 16-row column blocks (rows r and 16 + r of lane r) and calls
 // epi(ob, acc_c0, acc_c1) for the output blocks ob >= ob_first (earlier blocks belong
-// to orbitals the caller does not need).
-template <int HMAX, int NW, class Epi>
+// to orbitals the caller does not need). Hidden activations are carried as NT bf16
+// terms (one MFMA per term and weight fragment).
+template <int HMAX, int NW, int NT, class Epi>
 __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restrict__ W,
                                          const float* __restrict__ bias,
                                          const uint64_t (&xr)[2][NW], int lane, int ob_first,
                                          Epi&& epi) {
   constexpr int KB = HMAX / 32;
   const int g = lane >> 4;
-  bf16x8 chi[2][KB], clo[2][KB];
+  bf16x8 act[NT][2][KB];
   // ---- layer 0: exact 0/1 inputs, one MFMA per fragment
   {
     const int nk = M.nk[0], nob = M.nob[0];
@@ -202,14 +214,19 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
           }
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) split_relu(a0[c], a1[c], chi[c][kbo], clo[c][kbo]);
+        for (int c = 0; c < 2; ++c) {
+          bf16x8 t[NT];
+          split_relu<NT>(a0[c], a1[c], t);
+#pragma unroll
+          for (int i = 0; i < NT; ++i) act[i][c][kbo] = t[i];
+        }
       }
     }
   }
-  // ---- hidden layers 1..L-1: hi + lo activations
+  // ---- hidden layers 1..L-1
   for (int l = 1; l < M.L; ++l) {
     const int nk = M.nk[l], nob = M.nob[l];
-    bf16x8 nhi[2][KB], nlo[2][KB];
+    bf16x8 nxt[NT][2][KB];
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
@@ -224,28 +241,33 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
           if (kb < ke1) {
             const bf16x8 w1 = w1p[kb * 64];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              a1[c] = mfma_bf16(w1, chi[c][kb], a1[c]);
-              a1[c] = mfma_bf16(w1, clo[c][kb], a1[c]);
-            }
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+              for (int i = 0; i < NT; ++i) a1[c] = mfma_bf16(w1, act[i][c][kb], a1[c]);
             if (kb < ke0) {
               const bf16x8 w0 = w0p[kb * 64];
 #pragma unroll
-              for (int c = 0; c < 2; ++c) {
-                a0[c] = mfma_bf16(w0, chi[c][kb], a0[c]);
-                a0[c] = mfma_bf16(w0, clo[c][kb], a0[c]);
-              }
+              for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int i = 0; i < NT; ++i) a0[c] = mfma_bf16(w0, act[i][c][kb], a0[c]);
             }
           }
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) split_relu(a0[c], a1[c], nhi[c][kbo], nlo[c][kbo]);
+        for (int c = 0; c < 2; ++c) {
+          bf16x8 t[NT];
+          split_relu<NT>(a0[c], a1[c], t);
+#pragma unroll
+          for (int i = 0; i < NT; ++i) nxt[i][c][kbo] = t[i];
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) { chi[c][kb] = nhi[c][kb]; clo[c][kb] = nlo[c][kb]; }
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) act[i][c][kb] = nxt[i][c][kb];
   }
   // ---- output layer, block by block into the epilogue
   {
@@ -253,7 +275,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
 #pragma unroll 1
     for (int ob = sgpr(ob_first); ob < nob; ++ob) {
       f32x4 acc[2];
-      out_block<KB>(M, W, bias, chi, clo, ob, lane, acc);
+      out_block<KB, NT>(M, W, bias, act, ob, lane, acc);
       epi(ob, acc[0], acc[1]);
     }
   }
@@ -330,7 +352,7 @@ __device__ __forceinline__ int wave_min(int v) {
 
 // ----------------------------------------------------------------------------- sample pass
 // A(x), phi(x) and the per-orbital log p_p(s_p) of every sample (32 samples per wave step).
-template <int HMAX, int NW>
+template <int HMAX, int NW, int NT>
 __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -353,7 +375,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
   RowCounts rc[2] = {counts_before<NW>(xr[0], g), counts_before<NW>(xr[1], g)};
-  mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, 0, [&](int ob, const f32x4& a0, const f32x4& a1) {
+  mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, 0, [&](int ob, const f32x4& a0, const f32x4& a1) {
     const int p = 4 * ob + g;
     if (p < n) {
 #pragma unroll
@@ -403,7 +425,7 @@ struct SampleState {
 // every lane generates one entry (x', H_{x'x} in FP64, first changed orbital); the
 // network runs twice on 32 of them; every lane then forms H exp(dA + i dphi) in FP64
 // for its own entry. The item's partial sum (fixed order) goes to P.partial[item].
-template <int HMAX, int NW>
+template <int HMAX, int NW, int NT>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* __restrict__ W,
                                                const float* __restrict__ bias, WaveCtxBF16& wc,
                                                int64_t item, SampleState<NW>& st, int lane) {
@@ -464,7 +486,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       float zp[2] = {0.f, 0.f};
       const int pfirst = 4 * ob_first + g;
       RowCounts rc[2] = {counts_before<NW>(xr[0], pfirst), counts_before<NW>(xr[1], pfirst)};
-      mlp_bf16<HMAX, NW>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
+      mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
         const int p = 4 * ob + g;
         if (p < n) {
           const float lx = wc.lpx[p];
@@ -523,9 +545,9 @@ __device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* s
 
 // One system; a persistent grid strides over the work items, one wave per item. With
 // LDSW the packed weights and biases are first staged in LDS.
-template <int HMAX, int NW, bool LDSW>
-__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1) k_eval_bf16(EvalArgs P) {
-  constexpr int kEvalWaves = eval_waves_bf16(HMAX);
+template <int HMAX, int NW, int NT, bool LDSW>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16(EvalArgs P) {
+  constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   const bf16x8* W = (const bf16x8*)P.made.wfrag;
@@ -541,7 +563,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1) k_eval_bf16(Eva
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, NW>(P, W, bias, wc, item, st, lane);
+    eval_item_bf16<HMAX, NW, NT>(P, W, bias, wc, item, st, lane);
 }
 
 // Several systems in one persistent launch. Work is cut into chunks of kEvalWaves items
@@ -549,11 +571,11 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1) k_eval_bf16(Eva
 // [first[s], first[s+1]). Blocks stride over the chunks, so every block's share mixes
 // the systems in proportion and no system leaves a tail of its own. With LDSW a block
 // restages the weights whenever its next chunk belongs to another system.
-template <int HMAX, bool LDSW>
-__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1)
+template <int HMAX, int NT, bool LDSW>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
     k_eval_multi_bf16(const EvalArgs* __restrict__ args, const int64_t* __restrict__ first, int n_sys,
                       uint32_t lds_bias_off, uint32_t lds_ctx_off) {
-  constexpr int kEvalWaves = eval_waves_bf16(HMAX);
+  constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + lds_ctx_off))[wid];
@@ -585,8 +607,8 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX), 1)
     }
     const int64_t local = (chunk - first[s]) * kEvalWaves + wid;
     if (local < P.n_items) {
-      if (P.sys.W == 1) eval_item_bf16<HMAX, 1>(P, W, bias, wc, local, st1, lane);
-      else eval_item_bf16<HMAX, 2>(P, W, bias, wc, local, st2, lane);
+      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT>(P, W, bias, wc, local, st1, lane);
+      else eval_item_bf16<HMAX, 2, NT>(P, W, bias, wc, local, st2, lane);
     }
   }
 }
@@ -600,84 +622,77 @@ hipError_t launch_pack_bf16(const MadeDev& M, const ThetaLayout& T, const uint16
   return hipGetLastError();
 }
 
-template <int HMAX>
-static hipError_t rows_bf16_h(const RowsArgs& A, hipStream_t st) {
-  const int64_t waves = (A.B + 31) / 32;
-  const unsigned blocks = (unsigned)((waves + 3) / 4);
-  if (A.sys.W == 1) hipLaunchKernelGGL((k_rows_bf16<HMAX, 1>), dim3(blocks), dim3(256), 0, st, A);
-  else hipLaunchKernelGGL((k_rows_bf16<HMAX, 2>), dim3(blocks), dim3(256), 0, st, A);
-  return hipGetLastError();
+// Calls f(integral_constant<HMAX>, integral_constant<NT>) for the runtime width class
+// and activation-term count.
+template <class F>
+static hipError_t dispatch_shape(int hmax, int nt, F&& f) {
+  using std::integral_constant;
+  if (nt == 2) {
+    switch (hmax) {
+      case 32: return f(integral_constant<int, 32>{}, integral_constant<int, 2>{});
+      case 64: return f(integral_constant<int, 64>{}, integral_constant<int, 2>{});
+      case 128: return f(integral_constant<int, 128>{}, integral_constant<int, 2>{});
+      case 256: return f(integral_constant<int, 256>{}, integral_constant<int, 2>{});
+    }
+  } else if (nt == 3) {
+    switch (hmax) {
+      case 32: return f(integral_constant<int, 32>{}, integral_constant<int, 3>{});
+      case 64: return f(integral_constant<int, 64>{}, integral_constant<int, 3>{});
+      case 128: return f(integral_constant<int, 128>{}, integral_constant<int, 3>{});
+      case 256: return f(integral_constant<int, 256>{}, integral_constant<int, 3>{});
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, hipStream_t st) {
+template <class K>
+static hipError_t allow_lds(K kern, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t st) {
   if (A.B <= 0) return hipSuccess;
-  switch (hmax) {
-    case 32: return rows_bf16_h<32>(A, st);
-    case 64: return rows_bf16_h<64>(A, st);
-    case 128: return rows_bf16_h<128>(A, st);
-    case 256: return rows_bf16_h<256>(A, st);
-  }
-  return hipErrorInvalidValue;
+  return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
+    constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
+    const int64_t waves = (A.B + 31) / 32;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (A.sys.W == 1) hipLaunchKernelGGL((k_rows_bf16<HMAX, 1, NT>), dim3(blocks), dim3(256), 0, st, A);
+    else hipLaunchKernelGGL((k_rows_bf16<HMAX, 2, NT>), dim3(blocks), dim3(256), 0, st, A);
+    return hipGetLastError();
+  });
 }
 
-template <int HMAX, int NW, bool LDSW>
-static hipError_t eval_bf16_k(const EvalArgs& A, size_t lds, unsigned grid, hipStream_t st) {
-  auto kern = k_eval_bf16<HMAX, NW, LDSW>;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX)), lds, st, A);
-  return hipGetLastError();
-}
-
-template <int HMAX>
-static hipError_t eval_bf16_h(const EvalArgs& A, bool ldsw, size_t lds, unsigned grid, hipStream_t st) {
-  if (A.sys.W == 1)
-    return ldsw ? eval_bf16_k<HMAX, 1, true>(A, lds, grid, st) : eval_bf16_k<HMAX, 1, false>(A, lds, grid, st);
-  return ldsw ? eval_bf16_k<HMAX, 2, true>(A, lds, grid, st) : eval_bf16_k<HMAX, 2, false>(A, lds, grid, st);
-}
-
-template <int HMAX, bool LDSW>
-static hipError_t eval_multi_bf16_k(const EvalArgs* args, const int64_t* first, int n_sys, size_t lds,
-                                    uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st) {
-  auto kern = k_eval_multi_bf16<HMAX, LDSW>;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX)), lds, st, args, first, n_sys, bias_off, ctx_off);
-  return hipGetLastError();
-}
-
-template <int HMAX>
-static hipError_t eval_multi_bf16_h(const EvalArgs* args, const int64_t* first, int n_sys, bool ldsw, size_t lds,
-                                    uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st) {
-  return ldsw ? eval_multi_bf16_k<HMAX, true>(args, first, n_sys, lds, bias_off, ctx_off, grid, st)
-              : eval_multi_bf16_k<HMAX, false>(args, first, n_sys, lds, bias_off, ctx_off, grid, st);
-}
-
-hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, bool ldsw,
-                                  size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid, hipStream_t st) {
-  switch (hmax) {
-    case 32: return eval_multi_bf16_h<32>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
-    case 64: return eval_multi_bf16_h<64>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
-    case 128: return eval_multi_bf16_h<128>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
-    case 256: return eval_multi_bf16_h<256>(args, first, n_sys, ldsw, lds, bias_off, ctx_off, grid, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, bool ldsw, size_t lds, unsigned grid,
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, size_t lds, unsigned grid,
                             hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
-  switch (hmax) {
-    case 32: return eval_bf16_h<32>(A, ldsw, lds, grid, st);
-    case 64: return eval_bf16_h<64>(A, ldsw, lds, grid, st);
-    case 128: return eval_bf16_h<128>(A, ldsw, lds, grid, st);
-    case 256: return eval_bf16_h<256>(A, ldsw, lds, grid, st);
-  }
-  return hipErrorInvalidValue;
+  return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
+    constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
+    auto go = [&](auto kern) {
+      hipError_t e = allow_lds(kern, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, A);
+      return hipGetLastError();
+    };
+    if (A.sys.W == 1) return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true>) : go(k_eval_bf16<HMAX, 1, NT, false>);
+    return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true>) : go(k_eval_bf16<HMAX, 2, NT, false>);
+  });
+}
+
+hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
+                                  bool ldsw, size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid,
+                                  hipStream_t st) {
+  return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
+    constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
+    auto go = [&](auto kern) {
+      hipError_t e = allow_lds(kern, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, args, first, n_sys,
+                         bias_off, ctx_off);
+      return hipGetLastError();
+    };
+    return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true>) : go(k_eval_multi_bf16<HMAX, NT, false>);
+  });
 }
 
 }  // namespace elocal

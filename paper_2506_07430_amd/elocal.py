@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libelocal.so")
 
 FP64 = 0
-BF16 = 1
+BF16 = 1      # two bf16 terms per hidden activation
+BF16X3 = 2    # three bf16 terms per hidden activation
 OP_CONNECT, OP_EVAL, OP_GRAD = 0, 1, 2
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_CONFIG", 3: "E_WORKSPACE", 4: "E_NOMEM", 5: "E_DEVICE",
@@ -113,6 +114,8 @@ class Ansatz:
     def __init__(self, widths: Sequence[int], theta: torch.Tensor, precision: int):
         self.widths = tuple(int(w) for w in widths)
         self.precision = int(precision)
+        if precision not in (FP64, BF16, BF16X3):
+            raise ElocalError(1, f"unknown precision {precision}")
         want = torch.float64 if precision == FP64 else torch.bfloat16
         if theta.dtype != want or not theta.is_cuda or not theta.is_contiguous():
             raise ElocalError(1, f"theta must be a contiguous CUDA {want} tensor")

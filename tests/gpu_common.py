@@ -21,6 +21,7 @@ def theta_for(theta: np.ndarray, precision: int):
     """(device tensor for the library, FP64 values the oracle must use)."""
     if precision == elocal.FP64:
         return torch.tensor(theta, dtype=torch.float64).cuda(), np.asarray(theta, dtype=np.float64)
+    # ELOCAL_BF16 and ELOCAL_BF16X3 take the same bf16 parameters
     dev = torch.tensor(theta, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).cuda()
     return dev, obf16.round_to_bf16(theta)
 

@@ -126,6 +126,24 @@ def test_eval_bf16_c0():
     assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("precision", [elocal.BF16X3])
+def test_eval_bf16x3_c0_and_n24(precision):
+    """Three bf16 terms per activation: within 1e-5 Ha, and closer than two terms."""
+    p = synth.make_problem(0)
+    x = ansatz_samples(p, 1024, seed=0)
+    el3, _, th = _eval(p, x, precision)
+    el2, _, _ = _eval(p, x, elocal.BF16)
+    ref = _oracle_eloc(p, x, th)
+    e3, e2 = np.abs(el3 - ref), np.abs(el2 - ref)
+    print(f"c0: max |dE_loc| three terms {e3.max():.3e}, two terms {e2.max():.3e}")
+    assert e3.max() <= 1e-5 and e3.max() <= e2.max()
+    q = synth.make_problem(1, samples=64)
+    x = q.x[:6]
+    el3, _, th = _eval(q, x, precision)
+    ref = _oracle_eloc(q, x, th)
+    assert np.max(np.abs(el3 - ref)) <= 1e-5
+
+
 def test_eval_bf16_n24_sampled():
     """24 orbitals, 2 x 128 hidden: per-sample error and the weighted energy on a sample."""
     p = synth.make_problem(1, samples=64)
@@ -171,7 +189,7 @@ def test_stats_matches_oracle():
     assert np.allclose(st, ref, rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("precision", [elocal.FP64, elocal.BF16])
+@pytest.mark.parametrize("precision", [elocal.FP64, elocal.BF16, elocal.BF16X3])
 def test_grad_c0(precision):
     p = synth.make_problem(0)
     s = p.system
