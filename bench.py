@@ -32,6 +32,9 @@ PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 matrix peak
 PEAK_F64_TFLOPS = 78.6        # MI355X FP64 matrix/vector peak
 COUNTERS = os.path.join(ROOT, "profiles", "eval_bf16_n24_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_07430_amd", "csrc", "made_bf16.hip")
+CONNECT_COUNTERS = os.path.join(ROOT, "profiles", "connect_n24_counters.json")
+CONNECT_SRC = os.path.join(ROOT, "paper_2506_07430_amd", "csrc", "hamiltonian.hip")
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 
 
 def unmasked_weights(n: int, widths) -> int:
@@ -68,6 +71,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the captured step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--connect-reps", type=int, default=3,
+                    help="timed runs of the materialising generator (elocal_connect) on the whole batch; 0 skips")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size reference "
                          "for HBM byte counters)")
@@ -184,6 +189,38 @@ def main():
             "kernel": "k_eval_bf16", "kernel_ms": kern16_ms, "launches_timed": nl16,
             "alg_flops_per_row": 2 * uw, "dense_flops_per_row": 2 * dw,
             "dense_frac": B * (C - 1) * 2.0 * dw / (kern16_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS}
+
+    # --- the materialising generator + matrix elements (elocal_connect), HBM-write-bound:
+    # algorithmic bytes per listed pair = x' (8W) + H (8) + sign (1) + exc (4)
+    if args.connect_reps > 0:
+        W = ham.W
+        outs = (torch.empty((B, C, W), dtype=torch.int64, device=dev),
+                torch.empty((B, C), dtype=torch.float64, device=dev),
+                torch.empty((B, C), dtype=torch.int8, device=dev),
+                torch.empty((B, C), dtype=torch.int32, device=dev))
+        ham.connect(x, out=outs)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.connect_reps):
+            ham.connect(x, out=outs)
+        ev1.record()
+        torch.cuda.synchronize()
+        cms = ev0.elapsed_time(ev1) / args.connect_reps
+        per_pair = 8 * W + 8 + 1 + 4
+        alg = B * C * per_pair
+        ctraffic = None
+        if os.path.exists(CONNECT_COUNTERS):
+            with open(CONNECT_COUNTERS) as f:
+                cc = json.load(f)
+            if cc.get("kernel_src_sha256_16") == file_hash(CONNECT_SRC) and cc.get("samples") == B:
+                ctraffic = cc.get("hbm_bytes_per_launch")
+        out["connect"] = {"bound": "hbm", "ms": cms, "pairs_per_s": B * C / (cms * 1e-3),
+                          "bytes_per_pair": per_pair, "achieved": alg / (cms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": alg / (cms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": ctraffic,
+                          "note": "prep + generator launches on the caller's stream, HIP events around them"}
+        del outs
+        torch.cuda.empty_cache()
 
     # --- CPU oracle on a bounded sample (host cores), and the error of both GPU modes on it
     if not args.no_cpu:

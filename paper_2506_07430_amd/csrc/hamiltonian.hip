@@ -73,25 +73,37 @@ __global__ void __launch_bounds__(256) k_prep(SysDev S, const uint64_t* __restri
   for (int off = 32; off >= 1; off >>= 1) e += __shfl_xor(e, off);
   if (lane == 0) ediag[b] = e;
 
+  // singles: 8 at a time, lane = 8 * (single within the group) + (orbital residue mod 8);
+  // each lane sums its residue class of orbitals (so the 8 lanes of a single read one
+  // contiguous table row together), then a 3-step lane reduction
   const uint32_t nS = S.nSa + S.nSb;
   double* Fb = F + (size_t)b * nS;
-  for (uint32_t u = lane; u < nS; u += 64) {
-    const int s = (u < S.nSa) ? 0 : 1;
-    const uint32_t v = s ? u - S.nSa : u;
+  const int sub = lane >> 3, pg = lane & 7;
+  for (uint32_t u0 = 0; u0 < nS; u0 += 8) {
+    const uint32_t u = u0 + sub;
+    const bool valid = u < nS;
+    const uint32_t uu = valid ? u : 0;
+    const int s = (uu < S.nSa) ? 0 : 1;
+    const uint32_t v = s ? uu - S.nSa : uu;
     const int vs = s ? S.vb : S.va;
     const int i = c.occ[s][v / vs], a = c.vir[s][v % vs];
-    double f = S.h1e[a * n + i];
     const double* j3 = S.J3 + ((size_t)a * n + i) * n;
     const double* k3 = S.K3 + ((size_t)a * n + i) * n;
-    for (int p = 0; p < n; ++p) {
+    double f = 0.0;
+    for (int p = pg; p < n; p += 8) {
       const int nap = getbit<NW>(xv, 2 * p), nbp = getbit<NW>(xv, 2 * p + 1);
       f += (double)(nap + nbp) * j3[p] - (double)(s ? nbp : nap) * k3[p];
     }
-    Fb[u] = f;
+    f += __shfl_xor(f, 1);
+    f += __shfl_xor(f, 2);
+    f += __shfl_xor(f, 4);
+    if (valid && pg == 0) Fb[u] = S.h1e[a * n + i] + f;
   }
 }
 
 // One thread per list entry: unrank, apply the operators, look up the value, store.
+// The four output streams are written with nontemporal stores: they are consumed later,
+// and allocating them in L2 would evict the integral tables every entry reads.
 template <int NW>
 __global__ void __launch_bounds__(256) k_connect(SysDev S, const uint64_t* __restrict__ x,
                                                  int64_t B, uint32_t chunks,
@@ -115,12 +127,12 @@ __global__ void __launch_bounds__(256) k_connect(SysDev S, const uint64_t* __res
   const double v = excitation_value(S, e, F + (size_t)b * nS, ediag[b]);
   const size_t o = (size_t)b * S.C + t;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) xp[o * NW + w] = y[w];
-  hval[o] = sg < 0 ? -v : v;
-  sign[o] = (int8_t)sg;
+  for (int w = 0; w < NW; ++w) __builtin_nontemporal_store(y[w], xp + o * NW + w);
+  __builtin_nontemporal_store(sg < 0 ? -v : v, hval + o);
+  __builtin_nontemporal_store((int8_t)sg, sign + o);
   const uint32_t code = (uint32_t)(e.I < 0 ? 0xFF : e.I) | ((uint32_t)(e.J < 0 ? 0xFF : e.J) << 8) |
                         ((uint32_t)(e.A < 0 ? 0xFF : e.A) << 16) | ((uint32_t)(e.Bq < 0 ? 0xFF : e.Bq) << 24);
-  exc[o] = code;
+  __builtin_nontemporal_store(code, exc + o);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {

@@ -178,13 +178,24 @@ class Hamiltonian:
         return x.contiguous()
 
     # ------------------------------------------------------------------ calls
-    def connect(self, x: torch.Tensor, stream=None):
+    def connect(self, x: torch.Tensor, out=None, stream=None):
+        """(x' [B, C, W] int64, H [B, C] float64, sign [B, C] int8, exc [B, C] int32).
+
+        `out` may supply those four tensors (preallocated, contiguous)."""
         x = self._x(x)
         B = x.shape[0]
-        xp = torch.empty((B, self.C, self.W), dtype=torch.int64, device=x.device)
-        hv = torch.empty((B, self.C), dtype=torch.float64, device=x.device)
-        sg = torch.empty((B, self.C), dtype=torch.int8, device=x.device)
-        ex = torch.empty((B, self.C), dtype=torch.int32, device=x.device)
+        if out is None:
+            xp = torch.empty((B, self.C, self.W), dtype=torch.int64, device=x.device)
+            hv = torch.empty((B, self.C), dtype=torch.float64, device=x.device)
+            sg = torch.empty((B, self.C), dtype=torch.int8, device=x.device)
+            ex = torch.empty((B, self.C), dtype=torch.int32, device=x.device)
+        else:
+            xp, hv, sg, ex = out
+            shapes = ((B, self.C, self.W), (B, self.C), (B, self.C), (B, self.C))
+            dtypes = (torch.int64, torch.float64, torch.int8, torch.int32)
+            for t, sh, dt in zip(out, shapes, dtypes):
+                if tuple(t.shape) != sh or t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                    raise ElocalError(1, f"connect output must be a contiguous CUDA {dt} tensor of shape {sh}")
         ws, nb = self._workspace(OP_CONNECT, B)
         _check(lib().elocal_connect(self._h, _stream(stream), x.data_ptr(), B, ws.data_ptr(), nb,
                                     xp.data_ptr(), hv.data_ptr(), sg.data_ptr(), ex.data_ptr()))
