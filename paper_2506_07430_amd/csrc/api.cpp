@@ -138,7 +138,7 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   M.nbias = bo;
   // k-block ranges of the degree-sorted BF16 packing (FP64 packing is unsorted: full range)
   for (int l = 0; l <= L; ++l)
-    for (int ob = 0; ob < kMaxOutBlocks; ++ob) M.kend[l][ob] = (uint8_t)M.nk[l];
+    for (int ob = 0; ob < kMaxOutBlocks; ++ob) M.kend[l][ob] = M.nk[l];
   if (bf) {
     auto deg_at = [&](int width, int u) { return sorted_unit(n, width, u) % (n - 1) + 1; };
     auto count_le = [&](int width, int D) {
@@ -158,7 +158,7 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
           const int D = std::min(4 * ob + 3, n - 1);
           need = phase ? M.nin[l] : count_le(a->widths[L - 1], D);
         }
-        M.kend[l][ob] = (uint8_t)std::min(M.nk[l], (need + 31) / 32);
+        M.kend[l][ob] = std::min(M.nk[l], (need + 31) / 32);
       }
     }
   }

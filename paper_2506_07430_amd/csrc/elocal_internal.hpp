@@ -75,7 +75,8 @@ struct MadeDev {
   uint32_t nbias;              // total padded biases
   // BF16 packing stores hidden units sorted by degree; o-block ob of layer l then only
   // needs its first kend[l][ob] k-blocks (the rest of its weights are masked).
-  uint8_t kend[kMaxLayers][kMaxOutBlocks];
+  // (32-bit so that a wave-uniform lookup is a scalar load)
+  int32_t kend[kMaxLayers][kMaxOutBlocks];
   const void* wfrag;           // packed weights (bf16x8 per lane or double per lane)
   const void* bias;            // float (BF16 mode) or double (FP64 mode)
 };

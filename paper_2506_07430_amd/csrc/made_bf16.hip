@@ -281,36 +281,58 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
   }
 }
 
-// Per-row state of the epilogue: electrons of each spin in the orbitals before the
-// lane's next orbital (advanced by four orbitals per output block).
-struct RowCounts {
+// Per-row state of the epilogue at the lane's current orbital p: the row's occupation
+// bits from orbital p on (bit 0 = alpha of p) and the electrons of each spin before p.
+// Advanced by four orbitals per output block.
+template <int NW>
+struct RowCursor {
+  uint64_t bits[NW];
   int cu, cd;
 };
 
 template <int NW>
-__device__ __forceinline__ RowCounts counts_before(const uint64_t (&x)[NW], int p) {
-  RowCounts r;
+__device__ __forceinline__ RowCursor<NW> cursor_at(const uint64_t (&x)[NW], int p) {
+  RowCursor<NW> r;
   r.cu = count_spin_below<NW>(x, p, 0);
   r.cd = count_spin_below<NW>(x, p, 1);
+  const int k = 2 * p;   // < 64 NW for every orbital the epilogue visits
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    uint64_t v = 0;
+#pragma unroll
+    for (int u = w; u < NW; ++u) {
+      const int sh = 64 * (u - w) - k;   // bit i of word u lands at 64(u - w) + i - k
+      if (sh >= 0 && sh < 64) v |= x[u] << sh;
+      else if (sh < 0 && sh > -64) v |= x[u] >> (-sh);
+    }
+    r.bits[w] = v;
+  }
   return r;
+}
+
+template <int NW>
+__device__ __forceinline__ void cursor_advance4(RowCursor<NW>& r, uint32_t b8) {
+  r.cu += __popc(b8 & 0x55u);
+  r.cd += __popc(b8 & 0xAAu);
+#pragma unroll
+  for (int w = 0; w < NW; ++w) r.bits[w] = (r.bits[w] >> 8) | (w + 1 < NW ? r.bits[w + 1] << 56 : 0ull);
 }
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kLn2 = 0.6931471805599453094;
 
-// log2 p_p(s_p) for orbital p of row x, and advance the counts past orbitals p..p+3.
-// The softmax runs over the occupations that keep both electron counts reachable,
-// in base 2 on the native exp2/log2 units (one rescale to natural log per row, by the
-// caller); the exponentials are taken unshifted unless their sum leaves [1e-30, 1e30].
+// log2 p_p(s_p) of the row at the cursor's orbital, then advance the cursor by four
+// orbitals. The softmax runs over the occupations that keep both electron counts
+// reachable: alpha must be taken if cu < ta (= n_alpha - orbitals after p), may be
+// taken if cu < na (same for beta). Base 2 on the native exp2/log2 units (one rescale
+// to natural log per row, by the caller); the exponentials are taken unshifted unless
+// the log of their sum leaves (-99, 99).
 template <int NW>
-__device__ __forceinline__ float cond_log2p_step(const uint64_t (&x)[NW], int p, int n, int na, int nb,
-                                                 const f32x4& z, RowCounts& rc) {
-  const uint32_t b8 = bits8_at<NW>(x, 2 * p);
-  const uint32_t s = b8 & 3u;
-  const int left = n - p - 1;
-  const int ra = na - rc.cu, rb = nb - rc.cd;
-  const bool a_must = ra > left, a_may = ra > 0;
-  const bool b_must = rb > left, b_may = rb > 0;
+__device__ __forceinline__ float cond_log2p_step(RowCursor<NW>& rc, int ta, int tb, int na, int nb,
+                                                 const f32x4& z) {
+  const uint32_t b8 = (uint32_t)rc.bits[0] & 0xFFu;
+  const bool a_must = rc.cu < ta, a_may = rc.cu < na;
+  const bool b_must = rc.cd < tb, b_may = rc.cd < nb;
   const bool ok0 = !a_must && !b_must, ok1 = a_may && !b_must;
   const bool ok2 = !a_must && b_may, ok3 = a_may && b_may;
   const float y0 = z[0] * kLog2e, y1 = z[1] * kLog2e, y2 = z[2] * kLog2e, y3 = z[3] * kLog2e;
@@ -320,7 +342,7 @@ __device__ __forceinline__ float cond_log2p_step(const uint64_t (&x)[NW], int p,
   const float e3 = ok3 ? __builtin_amdgcn_exp2f(y3) : 0.f;
   const float sum = (e0 + e1) + (e2 + e3);
   float lse = __builtin_amdgcn_logf(sum);
-  if (__builtin_expect(!(sum > 1e-30f && sum < 1e30f), 0)) {
+  if (__builtin_expect(!(fabsf(lse) < 99.0f), 0)) {
     float m = -INFINITY;
     m = ok0 ? fmaxf(m, y0) : m;
     m = ok1 ? fmaxf(m, y1) : m;
@@ -330,11 +352,10 @@ __device__ __forceinline__ float cond_log2p_step(const uint64_t (&x)[NW], int p,
               (ok2 ? __builtin_amdgcn_exp2f(y2 - m) : 0.f) + (ok3 ? __builtin_amdgcn_exp2f(y3 - m) : 0.f);
     lse = m + __builtin_amdgcn_logf(t);
   }
-  const float y01 = (s & 1u) ? y1 : y0;
-  const float y23 = (s & 1u) ? y3 : y2;
-  const float ys = (s & 2u) ? y23 : y01;
-  rc.cu += __popc(b8 & 0x55u);
-  rc.cd += __popc(b8 & 0xAAu);
+  const float y01 = (b8 & 1u) ? y1 : y0;
+  const float y23 = (b8 & 1u) ? y3 : y2;
+  const float ys = (b8 & 2u) ? y23 : y01;
+  cursor_advance4<NW>(rc, b8);
   return ys - lse;
 }
 
@@ -374,13 +395,14 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
-  RowCounts rc[2] = {counts_before<NW>(xr[0], g), counts_before<NW>(xr[1], g)};
+  RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], min(g, n - 1)), cursor_at<NW>(xr[1], min(g, n - 1))};
   mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, 0, [&](int ob, const f32x4& a0, const f32x4& a1) {
     const int p = 4 * ob + g;
     if (p < n) {
+      const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const float lp = cond_log2p_step<NW>(xr[c], p, n, na, nb, c ? a1 : a0, rc[c]);
+        const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
         A[c] += (double)lp;
         if (rb[c] < P.B) P.lpx[rb[c] * n + p] = lp;     // log2 units
       }
@@ -470,8 +492,8 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
     const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
     double dA_own = 0.0;
     float zp_own = 0.f;
-    // ---- network on entries 32h .. 32h + 31
-#pragma unroll
+    // ---- network on entries 32h .. 32h + 31 (not unrolled: one copy of the network code)
+#pragma unroll 1
     for (int h = 0; h < 2; ++h) {
       uint64_t xr[2][NW];
       int p0[2];
@@ -484,16 +506,18 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       }
       double dA[2] = {0.0, 0.0};
       float zp[2] = {0.f, 0.f};
-      const int pfirst = 4 * ob_first + g;
-      RowCounts rc[2] = {counts_before<NW>(xr[0], pfirst), counts_before<NW>(xr[1], pfirst)};
+      const int pfirst = min(4 * ob_first + g, n - 1);
+      RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], pfirst), cursor_at<NW>(xr[1], pfirst)};
       mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
         const int p = 4 * ob + g;
         if (p < n) {
           const float lx = wc.lpx[p];
+          const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            const float lp = cond_log2p_step<NW>(xr[c], p, n, na, nb, c ? a1 : a0, rc[c]);
-            dA[c] += (double)(p >= p0[c] ? lp - lx : 0.f);
+            const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
+            const float d = p >= p0[c] ? lp - lx : 0.f;
+            dA[c] += (double)d;
           }
         }
         if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
@@ -512,10 +536,12 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
     }
     // ---- FP64 ratio and accumulation, one entry per lane
     if (t < S.C) {
-      const double dphi = 2.0 * M_PI * (1.0 / (1.0 + exp(-(double)zp_own)) - st.sig_x);
+      // phase difference 2 pi d with |d| < 1: sincospi needs no large-argument reduction;
+      // the magnitude exp(dA ln2 / 2) with dA in log2 units is exp2(dA / 2)
+      const double d = 1.0 / (1.0 + exp(-(double)zp_own)) - st.sig_x;
       double sn, cs;
-      sincos(dphi, &sn, &cs);
-      const double mag = hv * exp((0.5 * kLn2) * dA_own);
+      sincospi(2.0 * d, &sn, &cs);
+      const double mag = hv * exp2(0.5 * dA_own);
       acc_re += mag * cs;
       acc_im += mag * sn;
     }
