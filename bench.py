@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the captured step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--kpm-moments", type=int, default=64,
+                    help="Chebyshev moments of the KPM leg (12 orbitals, 6a+6b, 853,776 determinants); 0 skips")
     ap.add_argument("--connect-reps", type=int, default=3,
                     help="timed runs of the materialising generator (elocal_connect) on the whole batch; 0 skips")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -221,6 +223,32 @@ def main():
                           "note": "prep + generator launches on the caller's stream, HIP events around them"}
         del outs
         torch.cuda.empty_cache()
+
+    # --- KPM: Chebyshev moments on a full-sector vector (12 orbitals, 6a+6b); each step is
+    # one sector-wide H v (row-by-row generator + Slater--Condon + ranked gathers)
+    if args.kpm_moments > 0:
+        kp = synth.random_problem(12, 6, 6, (32,), seed=12, n_chol=16, decay=6.0, samples=1)
+        kham = elocal.Hamiltonian(kp.h1e, kp.eri, 12, 6, 6)
+        kdim = kham.sector_dim
+        g = torch.Generator(device="cpu").manual_seed(12)
+        alpha = torch.randn(kdim, generator=g, dtype=torch.float64).to(dev)
+        alpha /= alpha.norm()
+        scale = 4.0 * float(np.abs(kp.h1e).sum() + 0.5 * np.abs(kp.eri).sum())   # loose spectral bound
+        kham.kpm_moments(alpha, 4, scale, 0.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mu = kham.kpm_moments(alpha, args.kpm_moments, scale, 0.0)
+        e1.record()
+        torch.cuda.synchronize()
+        kms = e0.elapsed_time(e1)
+        steps = (args.kpm_moments) // 2
+        out["kpm"] = {"sector": "12 orbitals, 6a+6b", "dim": kdim, "connected_per_row": kham.C,
+                      "n_moments": args.kpm_moments, "ms": kms, "hv_ms": kms / max(steps, 1),
+                      "moments_per_s": args.kpm_moments / (kms * 1e-3),
+                      "h_elems_per_s": kdim * kham.C * steps / (kms * 1e-3),
+                      "omega_0": float(mu[0].item()), "max_abs_omega": float(mu.abs().max().item())}
+        del kham, alpha
 
     # --- CPU oracle on a bounded sample (host cores), and the error of both GPU modes on it
     if not args.no_cpu:

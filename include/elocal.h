@@ -185,6 +185,48 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s,
                                 double* const* logpsi);
 
 /*
+ * Full-sector vectors and the kernel polynomial method (Methods, KPM for absorption
+ * spectra; Results, KPM expansion of the dipole correlation function).
+ *
+ * A sector vector has one FP64 entry per determinant of the (n_alpha, n_beta) sector,
+ * dim = C(n, n_alpha) C(n, n_beta) entries, at index r = rank_a * C(n, n_beta) + rank_b,
+ * where the occupied spatial orbitals o_1 < ... < o_k of one spin have the
+ * combinatorial-number-system rank sum_i C(o_i, i) (i = 1..k). All vectors are device
+ * memory owned by the caller. H v is formed row by row from the same generator and
+ * Slater--Condon values as elocal_eval (nothing per row is stored); every sum has a fixed
+ * order, so results are bitwise repeatable.
+ *
+ * elocal_sector_dim: dim, or -1 when it exceeds 2^31 - 1 (the sector calls then fail with
+ *   ELOCAL_E_UNSUPPORTED).
+ * elocal_sector_workspace_bytes: workspace of elocal_sector_apply (kpm = 0) or of
+ *   elocal_kpm_moments (kpm = 1: three recursion vectors are included).
+ * elocal_sector_basis: x [dim][W], the determinant of every index.
+ * elocal_sector_apply: y = ch (H v) + cv v + cz z (z may be NULL; y must not alias v or z);
+ *   if dots is not NULL, dots[0] = <y|y> and dots[1] = <y|v> (device).
+ *   The dipole vector |alpha> = mu |0> (mu = -sum_pq d_pq sum_s a+_ps a_qs - mu_c) is
+ *   elocal_sector_apply on a handle created with h1e = -d and eri = 0, ch = 1, cv = -mu_c.
+ * elocal_kpm_moments: Omega_0 .. Omega_{n_moments-1} of |alpha> for H~ = (H - b) / a
+ *   (a > 0; the spectrum of H must lie inside (b - a, b + a)), by the recursion
+ *   a_1 = H~ a_0, a_{n+1} = 2 H~ a_n - a_{n-1} and moment doubling
+ *   Omega_{2n} = 2 <a_n|a_n> - Omega_0, Omega_{2n+1} = 2 <a_{n+1}|a_n> - Omega_1;
+ *   moments [n_moments] is device memory; ceil(n_moments / 2) applications of H.
+ * elocal_kpm_line_shape: rho(w~) = [g_0 Omega_0 + 2 sum_n g_n Omega_n T_n(w~)] /
+ *   (pi sqrt(1 - w~^2)) at n_points points w~ in (-1, 1), with the Jackson kernel
+ *   g_n = [(N - n + 1) cos(pi n / (N + 1)) + sin(pi n / (N + 1)) cot(pi / (N + 1))] / (N + 1),
+ *   N = n_moments; rho approximates sum_k |<k|alpha>|^2 delta(w~ - E~_k).
+ */
+int64_t elocal_sector_dim(elocal_t h);
+size_t elocal_sector_workspace_bytes(elocal_t h, int kpm);
+elocal_status elocal_sector_basis(elocal_t h, elocal_stream s, uint64_t* x);
+elocal_status elocal_sector_apply(elocal_t h, elocal_stream s, double ch, const double* v, double cv,
+                                  const double* z, double cz, double* y, void* ws, size_t ws_bytes,
+                                  double* dots);
+elocal_status elocal_kpm_moments(elocal_t h, elocal_stream s, const double* alpha, int64_t n_moments,
+                                 double a, double b, void* ws, size_t ws_bytes, double* moments);
+elocal_status elocal_kpm_line_shape(elocal_stream s, const double* moments, int64_t n_moments,
+                                    const double* w, int64_t n_points, double* rho);
+
+/*
  * Energy statistics (Methods, batch estimator): stats[4] = (Re<E>, Im<E>,
  * sum_i w_i |E_i - <E>|^2 / sum_i w_i, sum_i w_i), from eloc [B][2] and w [B]
  * (device). B >= 1; sum w must be > 0. Fixed-order FP64 reduction.

@@ -73,6 +73,9 @@ struct elocal_ctx {
   double* d_J3 = nullptr;
   double* d_K3 = nullptr;
   uint16_t* d_pairs = nullptr;
+  uint32_t* d_binom = nullptr;   // C(o, i) for o, i <= 64 (saturated), for full-sector ranks
+  int64_t sector_dim = -1;       // C(n, n_alpha) C(n, n_beta), -1 when above 2^31 - 1
+  uint32_t sector_nb = 0;        // C(n, n_beta)
   int cu_count = 256;
   // optional timing of the fused kernel
   static constexpr int kRing = 1024;
@@ -388,11 +391,27 @@ elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int
       for (int j = i + 1; j < ms[t]; ++j) pairs.push_back((uint16_t)(i | (j << 8)));
   }
   if (pairs.empty()) pairs.push_back(0);
+  std::vector<uint32_t> binom(65 * 65, 0);
+  for (int o = 0; o <= 64; ++o) {
+    uint64_t c = 1;   // C(o, 0); then C(o, i) = C(o, i - 1) (o - i + 1) / i, exact while small
+    bool big = false;
+    for (int i = 0; i <= 64; ++i) {
+      if (i > 0) {
+        if (i > o) c = 0;
+        else if (!big) {
+          const unsigned __int128 t = (unsigned __int128)c * (uint64_t)(o - i + 1);
+          c = (uint64_t)(t / (uint64_t)i);
+          big = c > 0xFFFFFFFFull;
+        }
+      }
+      binom[o * 65 + i] = (i > o) ? 0u : (big ? 0xFFFFFFFFu : (uint32_t)c);
+    }
+  }
   double* d_eri = nullptr;
   auto cleanup = [&](elocal_status st) {
     hipFree(d_eri);
     hipFree(h->d_h1e); hipFree(h->d_S); hipFree(h->d_J2); hipFree(h->d_K2);
-    hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs);
+    hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs); hipFree(h->d_binom);
     delete h;
     return st;
   };
@@ -400,12 +419,15 @@ elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int
       hipMalloc(&h->d_S, n4 * 8) != hipSuccess || hipMalloc(&h->d_J2, n2 * 8) != hipSuccess ||
       hipMalloc(&h->d_K2, n2 * 8) != hipSuccess || hipMalloc(&h->d_J3, n3 * 8) != hipSuccess ||
       hipMalloc(&h->d_K3, n3 * 8) != hipSuccess ||
-      hipMalloc(&h->d_pairs, pairs.size() * sizeof(uint16_t)) != hipSuccess)
+      hipMalloc(&h->d_pairs, pairs.size() * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc(&h->d_binom, binom.size() * sizeof(uint32_t)) != hipSuccess)
     return cleanup(fail(ELOCAL_E_NOMEM, "device allocation failed in elocal_create"));
   hipError_t err = hipMemcpy(h->d_h1e, h1e, n2 * 8, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(d_eri, eri, n4 * 8, hipMemcpyHostToDevice);
   if (err == hipSuccess)
     err = hipMemcpy(h->d_pairs, pairs.data(), pairs.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(h->d_binom, binom.data(), binom.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = launch_build_tables(n_orb, d_eri, h->d_S, h->d_J2, h->d_K2, h->d_J3, h->d_K3, nullptr);
   if (err == hipSuccess) err = hipDeviceSynchronize();
   if (err != hipSuccess) return cleanup(hip_fail(err, "elocal_create"));
@@ -417,6 +439,12 @@ elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int
   s.pair_va = h->d_pairs + poff[1];
   s.pair_ob = h->d_pairs + poff[2];
   s.pair_vb = h->d_pairs + poff[3];
+  {
+    const uint64_t ca = binom[n_orb * 65 + n_alpha], cb = binom[n_orb * 65 + n_beta];
+    const bool fits = ca < 0xFFFFFFFFull && cb < 0xFFFFFFFFull && ca * cb <= 0x7FFFFFFFull;
+    h->sector_dim = fits ? (int64_t)(ca * cb) : -1;
+    h->sector_nb = (uint32_t)cb;
+  }
   *out = h;
   return ELOCAL_OK;
 }
@@ -426,7 +454,7 @@ elocal_status elocal_destroy(elocal_t h) {
   for (hipEvent_t e : h->ev_start) hipEventDestroy(e);
   for (hipEvent_t e : h->ev_stop) hipEventDestroy(e);
   hipFree(h->d_h1e); hipFree(h->d_S); hipFree(h->d_J2); hipFree(h->d_K2);
-  hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs);
+  hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs); hipFree(h->d_binom);
   delete h;
   return ELOCAL_OK;
 }
@@ -681,6 +709,106 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
   }
   for (int i = 0; i < n_sys; ++i)
     if (B[i] > 0) HIP_TRY(launch_reduce(W[i].ediag, W[i].partial, B[i], M.p[i].ips, eloc[i], st), "reduce launch");
+  return ELOCAL_OK;
+}
+
+// ----------------------------------------------------------------------------- full sector / KPM
+namespace {
+
+struct SectorWs {
+  double* partial;   // [waves][2]
+  double* vec[3];    // recursion buffers (KPM only)
+  size_t bytes;
+  unsigned grid;
+};
+
+SectorWs carve_sector(const elocal_ctx* h, bool kpm, void* ws) {
+  SectorWs w{};
+  const int64_t dim = std::max<int64_t>(h->sector_dim, 1);
+  w.grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((dim + 3) / 4, (int64_t)h->cu_count * 8));
+  Carve c(ws);
+  w.partial = c.take<double>((size_t)w.grid * 4 * 2);
+  for (int k = 0; k < 3; ++k) w.vec[k] = kpm ? c.take<double>((size_t)dim) : nullptr;
+  w.bytes = c.off;
+  return w;
+}
+
+elocal_status check_sector(const elocal_ctx* h) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (h->sector_dim < 0)
+    return fail(ELOCAL_E_UNSUPPORTED, "sector dimension of (%d, %d, %d) exceeds 2^31 - 1", h->sys.n, h->sys.na,
+                h->sys.nb);
+  return ELOCAL_OK;
+}
+
+}  // namespace
+
+int64_t elocal_sector_dim(elocal_t h) { return h ? h->sector_dim : -1; }
+
+size_t elocal_sector_workspace_bytes(elocal_t h, int kpm) {
+  if (check_sector(h)) return 0;
+  return carve_sector(h, kpm != 0, nullptr).bytes;
+}
+
+elocal_status elocal_sector_basis(elocal_t h, elocal_stream s, uint64_t* x) {
+  if (elocal_status e = check_sector(h)) return e;
+  if (!x) return fail(ELOCAL_E_INVALID, "x is null");
+  if (elocal_status st = check_device(h)) return st;
+  HIP_TRY(launch_sector_basis(h->sys, h->d_binom, h->sector_dim, h->sector_nb, x, (hipStream_t)s), "basis launch");
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_sector_apply(elocal_t h, elocal_stream s, double ch, const double* v, double cv, const double* z,
+                                  double cz, double* y, void* ws, size_t ws_bytes, double* dots) {
+  if (elocal_status e = check_sector(h)) return e;
+  if (!v || !y || !ws) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  if (y == v || (z && y == z)) return fail(ELOCAL_E_INVALID, "y must not alias v or z");
+  const SectorWs need = carve_sector(h, false, nullptr);
+  if (ws_bytes < need.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const SectorWs w = carve_sector(h, false, ws);
+  hipStream_t st = (hipStream_t)s;
+  HIP_TRY(launch_sector_apply(h->sys, h->d_binom, h->sector_dim, h->sector_nb, ch, cv, v, cz, z, y, w.partial, w.grid,
+                              st), "sector apply launch");
+  if (dots) HIP_TRY(launch_sector_dots(w.partial, (int64_t)w.grid * 4, dots, nullptr, -1, 0, st), "dots launch");
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_kpm_moments(elocal_t h, elocal_stream s, const double* alpha, int64_t n_moments, double a,
+                                 double b, void* ws, size_t ws_bytes, double* moments) {
+  if (elocal_status e = check_sector(h)) return e;
+  if (!alpha || !ws || !moments) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  if (n_moments < 1) return fail(ELOCAL_E_INVALID, "n_moments=%lld < 1", (long long)n_moments);
+  if (!(a > 0.0)) return fail(ELOCAL_E_INVALID, "scale a=%g must be positive", a);
+  const SectorWs need = carve_sector(h, true, nullptr);
+  if (ws_bytes < need.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const SectorWs w = carve_sector(h, true, ws);
+  hipStream_t st = (hipStream_t)s;
+  const int64_t dim = h->sector_dim, nw = (int64_t)w.grid * 4;
+  HIP_TRY(launch_norm2(alpha, dim, moments, st), "norm launch");   // Omega_0
+  // a_1 = (H - b) a_0 / a; then a_{n+1} = 2 (H - b) a_n / a - a_{n-1}
+  const double* prev = nullptr;
+  const double* cur = alpha;
+  int slot = 0;
+  for (int64_t n = 0; 2 * n + 1 < n_moments; ++n) {
+    double* nxt = w.vec[slot];
+    const double ch = (n == 0 ? 1.0 : 2.0) / a, cv = -(n == 0 ? 1.0 : 2.0) * b / a;
+    HIP_TRY(launch_sector_apply(h->sys, h->d_binom, dim, h->sector_nb, ch, cv, cur, -1.0, prev, nxt, w.partial,
+                                w.grid, st), "sector apply launch");
+    HIP_TRY(launch_sector_dots(w.partial, nw, nullptr, moments, n, n_moments, st), "moments launch");
+    prev = cur;
+    cur = nxt;
+    slot = (slot + 1) % 3;
+  }
+  return ELOCAL_OK;
+}
+
+elocal_status elocal_kpm_line_shape(elocal_stream s, const double* moments, int64_t n_moments, const double* w,
+                                    int64_t n_points, double* rho) {
+  if (!moments || !w || !rho) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  if (n_moments < 1 || n_points < 0) return fail(ELOCAL_E_INVALID, "n_moments < 1 or n_points < 0");
+  HIP_TRY(launch_line_shape(moments, n_moments, w, n_points, rho, (hipStream_t)s), "line shape launch");
   return ELOCAL_OK;
 }
 

@@ -280,4 +280,59 @@ __device__ __forceinline__ void build_ctx(const SysDev& S, const uint64_t (&x)[N
   if (lane < NW) c.x[lane] = x[lane];
 }
 
+// Diagonal energy and the value of every single excitation of one sample (one wave; the
+// occupied/virtual lists `c` must be visible to the whole wave):
+//   E_diag = sum_p n_p h_pp + 1/2 sum_pq [n_p n_q (pp|qq) - sum_s n_ps n_qs (pq|qp)]
+//   F_ai   = h_ai + sum_p n_p (ai|pp) - sum_p n_{p,s} (ap|pi)        (i -> a of spin s)
+// Writes F[0 .. nSa + nSb) (single index as in the canonical list) and returns E_diag
+// (the same value in every lane). Sums run in a fixed order (bitwise repeatable).
+template <int NW>
+__device__ __forceinline__ double sample_terms(const SysDev& S, const uint64_t (&xv)[NW], const SampleCtx& c,
+                                               int lane, double* __restrict__ Fb) {
+  const int n = S.n;
+  double e = 0.0;
+  if (lane < n) {
+    const int p = lane;
+    const int nap = getbit<NW>(xv, 2 * p), nbp = getbit<NW>(xv, 2 * p + 1);
+    const int np_ = nap + nbp;
+    if (np_) {
+      double row = np_ * S.h1e[p * n + p];
+      double two = 0.0;
+      for (int q = 0; q < n; ++q) {
+        const int naq = getbit<NW>(xv, 2 * q), nbq = getbit<NW>(xv, 2 * q + 1);
+        two += (double)(np_ * (naq + nbq)) * S.J2[p * n + q] - (double)(nap * naq + nbp * nbq) * S.K2[p * n + q];
+      }
+      e = row + 0.5 * two;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) e += __shfl_xor(e, off);
+  // singles: 8 at a time, lane = 8 * (single within the group) + (orbital residue mod 8);
+  // each lane sums its residue class of orbitals (so the 8 lanes of a single read one
+  // contiguous table row together), then a 3-step lane reduction
+  const uint32_t nS = S.nSa + S.nSb;
+  const int sub = lane >> 3, pg = lane & 7;
+  for (uint32_t u0 = 0; u0 < nS; u0 += 8) {
+    const uint32_t u = u0 + sub;
+    const bool valid = u < nS;
+    const uint32_t uu = valid ? u : 0;
+    const int s = (uu < S.nSa) ? 0 : 1;
+    const uint32_t v = s ? uu - S.nSa : uu;
+    const int vs = s ? S.vb : S.va;
+    const int i = c.occ[s][v / vs], a = c.vir[s][v % vs];
+    const double* j3 = S.J3 + ((size_t)a * n + i) * n;
+    const double* k3 = S.K3 + ((size_t)a * n + i) * n;
+    double f = 0.0;
+    for (int p = pg; p < n; p += 8) {
+      const int nap = getbit<NW>(xv, 2 * p), nbp = getbit<NW>(xv, 2 * p + 1);
+      f += (double)(nap + nbp) * j3[p] - (double)(s ? nbp : nap) * k3[p];
+    }
+    f += __shfl_xor(f, 1);
+    f += __shfl_xor(f, 2);
+    f += __shfl_xor(f, 4);
+    if (valid && pg == 0) Fb[u] = S.h1e[a * n + i] + f;
+  }
+  return e;
+}
+
 }  // namespace elocal

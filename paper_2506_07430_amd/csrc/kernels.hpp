@@ -86,6 +86,18 @@ hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream
 hipError_t launch_reduce(const double* ediag, const double* partial, int64_t B, uint32_t ips,
                          double* eloc, hipStream_t st);
 
+// Full-sector vectors (index = rank_alpha * C(n, n_beta) + rank_beta; binom[o * 65 + i] =
+// C(o, i), saturated at 2^32 - 1) and the KPM recursion on them.
+hipError_t launch_sector_apply(const SysDev& S, const uint32_t* binom, int64_t dim, uint32_t nb_dim, double ch,
+                               double cv, const double* v, double cz, const double* z, double* y, double* partial,
+                               unsigned grid, hipStream_t st);
+hipError_t launch_sector_dots(const double* partial, int64_t nw, double* dots, double* mu, int64_t n,
+                              int64_t n_moments, hipStream_t st);
+hipError_t launch_norm2(const double* v, int64_t dim, double* out, hipStream_t st);
+hipError_t launch_sector_basis(const SysDev& S, const uint32_t* binom, int64_t dim, uint32_t nb_dim, uint64_t* x,
+                               hipStream_t st);
+hipError_t launch_line_shape(const double* mu, int64_t N, const double* w, int64_t P, double* rho, hipStream_t st);
+
 // Statistics and gradient (FP64).
 hipError_t launch_stats(const double* eloc, const double* w, int64_t B, double* stats, hipStream_t st);
 

@@ -1,0 +1,251 @@
+// Full-sector vectors and the Chebyshev (KPM) recursion on them.
+//
+// A vector of the (n_alpha, n_beta) sector has one entry per determinant, at index
+// r = rank(alpha set) * C(n, n_beta) + rank(beta set), where a set of occupied spatial
+// orbitals o_1 < ... < o_k has the combinatorial-number-system rank sum_i C(o_i, i).
+// H v is formed row by row ("pull"): one wave per row unranks the row's determinant,
+// builds its occupied/virtual lists and single-excitation values in LDS, walks the
+// row's canonical connected list (the same generator and Slater--Condon values as the
+// local-energy path), ranks every x' and gathers v there. The row's sum, a fixed xor
+// tree over the wave, is bitwise repeatable; nothing per row is stored in HBM.
+#include "elocal_internal.hpp"
+#include "kernels.hpp"
+
+namespace elocal {
+
+// Determinant of rank (ra, rb): greedy unranking of each spin's set.
+template <int NW>
+__device__ __forceinline__ void sector_unrank(const uint32_t* __restrict__ binom, int n, int na, int nb,
+                                              uint32_t ra, uint32_t rb, uint64_t (&x)[NW]) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) x[w] = 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    uint32_t r = s ? rb : ra;
+    int o = n - 1;
+    for (int i = s ? nb : na; i >= 1; --i) {
+      while (binom[o * 65 + i] > r) --o;
+      r -= binom[o * 65 + i];
+      const int k = 2 * o + s;
+      x[k >> 6] |= 1ull << (k & 63);
+      --o;
+    }
+  }
+}
+
+// Rank of one spin's set of occupied orbitals (ascending set bits).
+template <int NW>
+__device__ __forceinline__ uint32_t spin_rank(const uint32_t* __restrict__ binom, const uint64_t (&x)[NW], int s) {
+  const uint64_t pat = s ? 0xAAAAAAAAAAAAAAAAull : 0x5555555555555555ull;
+  uint32_t r = 0;
+  int i = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    uint64_t m = x[w] & pat;
+    while (m) {
+      const int k = 64 * w + __ffsll((unsigned long long)m) - 1;
+      ++i;
+      r += binom[(k >> 1) * 65 + i];
+      m &= m - 1;
+    }
+  }
+  return r;
+}
+
+// y = ch (H v) + cv v + cz z over the whole sector (z may be null); per wave, the
+// partial sums of y.y and y.v over its rows (fixed row order) go to partial[wave].
+// LDS per wave (stride `wstride` bytes): the row's SampleCtx, then its nSa + nSb
+// single-excitation values.
+template <int NW>
+__global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* __restrict__ binom, int64_t dim,
+                                                      uint32_t nb_dim, double ch, double cv,
+                                                      const double* __restrict__ v, double cz,
+                                                      const double* __restrict__ z, double* __restrict__ y,
+                                                      double* __restrict__ partial, uint32_t wstride) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  struct {
+    SampleCtx& c;
+    double* F;
+  } wc{*(SampleCtx*)(smem + wid * wstride), (double*)(smem + wid * wstride + sizeof(SampleCtx))};
+  const int64_t wave = (int64_t)blockIdx.x * 4 + wid, nwaves = (int64_t)gridDim.x * 4;
+  double yy = 0.0, yv = 0.0;
+  for (int64_t r = wave; r < dim; r += nwaves) {
+    const uint32_t ra = (uint32_t)(r / nb_dim), rb = (uint32_t)(r % nb_dim);
+    uint64_t x[NW];
+    sector_unrank<NW>(binom, S.n, S.na, S.nb, ra, rb, x);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    build_ctx<NW>(S, x, wc.c, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double ed = sample_terms<NW>(S, x, wc.c, lane, wc.F);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double acc = 0.0;
+    for (uint32_t t0 = 0; t0 < S.C; t0 += 64) {
+      const uint32_t t = t0 + lane;
+      if (t < S.C) {
+        const Excitation e = unrank(S, wc.c, t);
+        uint64_t xo[NW];
+        const int sg = apply_excitation<NW>(x, e, xo);
+        const double val = excitation_value(S, e, wc.F, ed);
+        const int64_t idx = (int64_t)spin_rank<NW>(binom, xo, 0) * nb_dim + spin_rank<NW>(binom, xo, 1);
+        acc += (sg < 0 ? -val : val) * v[idx];
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    const double vr = v[r];
+    double yr = ch * acc + cv * vr;
+    if (z) yr += cz * z[r];
+    if (lane == 0) y[r] = yr;
+    yy += yr * yr;
+    yv += yr * vr;
+  }
+  if (lane == 0) {
+    partial[2 * wave] = yy;
+    partial[2 * wave + 1] = yv;
+  }
+}
+
+// Basis enumeration: x[r] for every r (one thread per row).
+template <int NW>
+__global__ void k_sector_basis(SysDev S, const uint32_t* __restrict__ binom, int64_t dim, uint32_t nb_dim,
+                               uint64_t* __restrict__ x) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= dim) return;
+  uint64_t w[NW];
+  sector_unrank<NW>(binom, S.n, S.na, S.nb, (uint32_t)(r / nb_dim), (uint32_t)(r % nb_dim), w);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[r * NW + k] = w[k];
+}
+
+// Sum of the per-wave partials in a fixed tree (one block); then, for the KPM recursion,
+// the moments of step n (Omega_{2n+1} = 2 <a_{n+1}|a_n> - Omega_1, Omega_{2n+2} =
+// 2 <a_{n+1}|a_{n+1}> - Omega_0) or, for n < 0, just the two sums into dots.
+__global__ void __launch_bounds__(1024) k_sector_dots(const double* __restrict__ partial, int64_t nw,
+                                                      double* __restrict__ dots, double* __restrict__ mu,
+                                                      int64_t n, int64_t n_moments) {
+  __shared__ double s0[1024], s1[1024];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < nw; i += 1024) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 512; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s0[threadIdx.x] += s0[threadIdx.x + off];
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double yy = s0[0], yv = s1[0];
+    if (dots) {
+      dots[0] = yy;
+      dots[1] = yv;
+    }
+    if (mu) {
+      if (n == 0) {            // y = a_1 = H~ a_0: Omega_1 = <a_1|a_0>, Omega_2 = 2 <a_1|a_1> - Omega_0
+        if (1 < n_moments) mu[1] = yv;
+        if (2 < n_moments) mu[2] = 2.0 * yy - mu[0];
+      } else {                 // y = a_{n+1}
+        if (2 * n + 1 < n_moments) mu[2 * n + 1] = 2.0 * yv - mu[1];
+        if (2 * n + 2 < n_moments) mu[2 * n + 2] = 2.0 * yy - mu[0];
+      }
+    }
+  }
+}
+
+// Omega_0 = <a_0|a_0> (fixed tree, one block).
+__global__ void __launch_bounds__(1024) k_norm2(const double* __restrict__ v, int64_t dim, double* __restrict__ out) {
+  __shared__ double s[1024];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < dim; i += 1024) a += v[i] * v[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 512; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// Jackson-damped line shape: rho(w) = [g_0 Omega_0 + 2 sum_n g_n Omega_n T_n(w)] /
+// (pi sqrt(1 - w^2)), T_n by the three-term recurrence; one thread per point.
+__global__ void k_line_shape(const double* __restrict__ mu, int64_t N, const double* __restrict__ w, int64_t P,
+                             double* __restrict__ rho) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  const double x = w[j];
+  const double q = M_PI / (double)(N + 1), cq = cos(q) / sin(q);
+  double t_prev = 1.0, t_cur = x;
+  double s = mu[0];   // g_0 = 1
+  for (int64_t n = 1; n < N; ++n) {
+    double sn, cn;
+    sincospi((double)n / (double)(N + 1), &sn, &cn);
+    const double g = ((double)(N - n + 1) * cn + sn * cq) / (double)(N + 1);
+    s += 2.0 * g * mu[n] * t_cur;
+    const double t_next = 2.0 * x * t_cur - t_prev;
+    t_prev = t_cur;
+    t_cur = t_next;
+  }
+  rho[j] = s / (M_PI * sqrt(1.0 - x * x));
+}
+
+// ----------------------------------------------------------------------------- launchers
+hipError_t launch_sector_apply(const SysDev& S, const uint32_t* binom, int64_t dim, uint32_t nb_dim, double ch,
+                               double cv, const double* v, double cz, const double* z, double* y, double* partial,
+                               unsigned grid, hipStream_t st) {
+  if (dim <= 0) return hipSuccess;
+  const uint32_t nS = S.nSa + S.nSb;
+  const uint32_t wstride = (uint32_t)((sizeof(SampleCtx) + 8u * (nS ? nS : 1u) + 15u) & ~15u);
+  const size_t lds = 4u * wstride;
+  if (lds > 65536) {
+    auto kern = (S.W == 1) ? (const void*)k_sector_apply<1> : (const void*)k_sector_apply<2>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (S.W == 1)
+    hipLaunchKernelGGL(k_sector_apply<1>, dim3(grid), dim3(256), lds, st, S, binom, dim, nb_dim, ch, cv, v, cz, z, y,
+                       partial, wstride);
+  else
+    hipLaunchKernelGGL(k_sector_apply<2>, dim3(grid), dim3(256), lds, st, S, binom, dim, nb_dim, ch, cv, v, cz, z, y,
+                       partial, wstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_sector_dots(const double* partial, int64_t nw, double* dots, double* mu, int64_t n,
+                              int64_t n_moments, hipStream_t st) {
+  hipLaunchKernelGGL(k_sector_dots, dim3(1), dim3(1024), 0, st, partial, nw, dots, mu, n, n_moments);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(const double* v, int64_t dim, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, v, dim, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sector_basis(const SysDev& S, const uint32_t* binom, int64_t dim, uint32_t nb_dim, uint64_t* x,
+                               hipStream_t st) {
+  if (dim <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((dim + 255) / 256);
+  if (S.W == 1) hipLaunchKernelGGL(k_sector_basis<1>, dim3(blocks), dim3(256), 0, st, S, binom, dim, nb_dim, x);
+  else hipLaunchKernelGGL(k_sector_basis<2>, dim3(blocks), dim3(256), 0, st, S, binom, dim, nb_dim, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_line_shape(const double* mu, int64_t N, const double* w, int64_t P, double* rho, hipStream_t st) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_line_shape, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, mu, N, w, P, rho);
+  return hipGetLastError();
+}
+
+}  // namespace elocal

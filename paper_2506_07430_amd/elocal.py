@@ -67,12 +67,22 @@ def lib():
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
         L.elocal_tune.argtypes = [vp, i32, i64]
+        L.elocal_sector_dim.argtypes = [vp]
+        L.elocal_sector_dim.restype = i64
+        L.elocal_sector_workspace_bytes.argtypes = [vp, i32]
+        L.elocal_sector_workspace_bytes.restype = sz
+        L.elocal_sector_basis.argtypes = [vp, vp, vp]
+        dbl = ctypes.c_double
+        L.elocal_sector_apply.argtypes = [vp, vp, dbl, vp, dbl, vp, dbl, vp, vp, sz, vp]
+        L.elocal_kpm_moments.argtypes = [vp, vp, vp, i64, dbl, dbl, vp, sz, vp]
+        L.elocal_kpm_line_shape.argtypes = [vp, vp, i64, vp, i64, vp]
         L.elocal_workspace_bytes_multi.argtypes = [i32, P(vp), P(P(_Ansatz)), P(i64)]
         L.elocal_workspace_bytes_multi.restype = sz
         L.elocal_eval_multi.argtypes = [i32, P(vp), vp, P(P(_Ansatz)), P(vp), P(i64), vp, sz, P(vp), P(vp)]
         for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
                   "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune",
-                  "elocal_eval_multi"):
+                  "elocal_eval_multi", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
+                  "elocal_kpm_line_shape"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -82,7 +92,9 @@ def exported_symbols() -> Sequence[str]:
     return ["elocal_create", "elocal_destroy", "elocal_num_connected", "elocal_words", "elocal_num_params",
             "elocal_workspace_bytes", "elocal_connect", "elocal_eval", "elocal_stats", "elocal_grad",
             "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune", "elocal_last_error",
-            "elocal_workspace_bytes_multi", "elocal_eval_multi"]
+            "elocal_workspace_bytes_multi", "elocal_eval_multi", "elocal_sector_dim",
+            "elocal_sector_workspace_bytes", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
+            "elocal_kpm_line_shape"]
 
 
 def _check(status: int):
@@ -246,6 +258,54 @@ class Hamiltonian:
         _check(lib().elocal_tune(self._h, 0, int(grid)))
         _check(lib().elocal_tune(self._h, 1, int(groups)))
 
+    # ------------------------------------------------------------------ full sector / KPM
+    @property
+    def sector_dim(self) -> int:
+        return int(lib().elocal_sector_dim(self._h))
+
+    def _sector_ws(self, kpm: bool) -> Tuple[torch.Tensor, int]:
+        need = int(lib().elocal_sector_workspace_bytes(self._h, int(kpm)))
+        if need == 0:
+            raise ElocalError(6, lib().elocal_last_error().decode())
+        key = "sector_kpm" if kpm else "sector"
+        buf = self._ws.get(key)
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[key] = buf
+        return buf, buf.numel()
+
+    def sector_basis(self, stream=None) -> torch.Tensor:
+        """Every determinant of the sector, [dim, W] int64 (row r = index r)."""
+        if self.sector_dim < 0:
+            raise ElocalError(6, "sector dimension exceeds 2^31 - 1")
+        x = torch.empty((self.sector_dim, self.W), dtype=torch.int64, device=self.device)
+        _check(lib().elocal_sector_basis(self._h, _stream(stream), x.data_ptr()))
+        return x
+
+    def sector_apply(self, v: torch.Tensor, ch: float = 1.0, cv: float = 0.0, z: Optional[torch.Tensor] = None,
+                     cz: float = 0.0, out: Optional[torch.Tensor] = None, dots: bool = False, stream=None):
+        """y = ch H v + cv v + cz z over the sector; with dots, also (<y|y>, <y|v>)."""
+        dim = self.sector_dim
+        for t in (v, z):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or t.numel() != dim or not t.is_contiguous()):
+                raise ElocalError(1, f"sector vectors must be contiguous CUDA float64 of {dim} entries")
+        y = out if out is not None else torch.empty(dim, dtype=torch.float64, device=v.device)
+        d = torch.empty(2, dtype=torch.float64, device=v.device) if dots else None
+        ws, nb = self._sector_ws(False)
+        _check(lib().elocal_sector_apply(self._h, _stream(stream), float(ch), v.data_ptr(), float(cv), _ptr(z),
+                                         float(cz), y.data_ptr(), ws.data_ptr(), nb, _ptr(d)))
+        return (y, d) if dots else y
+
+    def kpm_moments(self, alpha: torch.Tensor, n_moments: int, a: float, b: float, stream=None) -> torch.Tensor:
+        """Chebyshev moments Omega_0..Omega_{N-1} of alpha for H~ = (H - b) / a."""
+        if alpha.dtype != torch.float64 or not alpha.is_cuda or alpha.numel() != self.sector_dim:
+            raise ElocalError(1, "alpha must be a CUDA float64 sector vector")
+        mu = torch.empty(int(n_moments), dtype=torch.float64, device=alpha.device)
+        ws, nb = self._sector_ws(True)
+        _check(lib().elocal_kpm_moments(self._h, _stream(stream), alpha.contiguous().data_ptr(), int(n_moments),
+                                        float(a), float(b), ws.data_ptr(), nb, mu.data_ptr()))
+        return mu
+
     def check_samples(self, x: torch.Tensor, stream=None) -> int:
         x = self._x(x)
         ws = torch.empty(8, dtype=torch.uint8, device=x.device)
@@ -258,6 +318,16 @@ class Hamiltonian:
 
 
 MAX_SYSTEMS = 16
+
+
+def kpm_line_shape(moments: torch.Tensor, w: torch.Tensor, stream=None) -> torch.Tensor:
+    """Jackson-damped line shape rho(w~) from the moments, at points w~ in (-1, 1)."""
+    moments = moments.to(torch.float64).contiguous()
+    w = w.to(torch.float64).contiguous()
+    rho = torch.empty_like(w)
+    _check(lib().elocal_kpm_line_shape(_stream(stream), moments.data_ptr(), moments.numel(), w.data_ptr(),
+                                       w.numel(), rho.data_ptr()))
+    return rho
 
 
 class MultiEval:

@@ -35,7 +35,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 SEED_ROOT = 250607430
-STREAM_H1E, STREAM_ERI, STREAM_PARAMS, STREAM_SAMPLES, STREAM_MULT, STREAM_FD = range(6)
+STREAM_H1E, STREAM_ERI, STREAM_PARAMS, STREAM_SAMPLES, STREAM_MULT, STREAM_FD, STREAM_DIPOLE = range(7)
 
 
 def rng(cfg: int, stream: int, system: int = 0) -> np.random.Generator:
@@ -123,6 +123,19 @@ def make_eri(sys: System, cfg: int, system_index: int = 0) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------- parameters
+def make_dipole(n: int, seed: int) -> np.ndarray:
+    """Synthetic dipole integrals d_pq (one Cartesian component), symmetric: a chain-like
+    position on the diagonal, (p - (n - 1) / 2) / 2, plus N(0, 0.05) couplings damped by
+    exp(-|p - q|) (molecular dipole integrals are not available)."""
+    g = rng(seed, STREAM_DIPOLE)
+    d = np.diag((np.arange(n) - (n - 1) / 2.0) / 2.0)
+    iu = np.triu_indices(n, 1)
+    off = g.normal(0.0, 0.05, iu[0].size) * np.exp(-np.abs(iu[0] - iu[1]))
+    d[iu] = off
+    d[(iu[1], iu[0])] = off
+    return d
+
+
 def num_params(n: int, widths: Sequence[int]) -> int:
     """Length of the flat parameter vector (layout documented in include/elocal.h)."""
     dims = [2 * n] + list(widths) + [4 * n]
