@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the captured step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--pauli-samples", type=int, default=1024,
+                    help="samples of the Pauli-string route leg (Algorithm 1 over unique flips); 0 skips")
     ap.add_argument("--kpm-moments", type=int, default=64,
                     help="Chebyshev moments of the KPM leg (12 orbitals, 6a+6b, 853,776 determinants); 0 skips")
     ap.add_argument("--connect-reps", type=int, default=3,
@@ -223,6 +225,32 @@ def main():
                           "note": "prep + generator launches on the caller's stream, HIP events around them"}
         del outs
         torch.cuda.empty_cache()
+
+    # --- the paper's Pauli-string route on the same ansatz and samples: every unique flip
+    # of the Jordan--Wigner strings goes through the ansatz (vs the C connected ones)
+    if args.pauli_samples > 0:
+        Bp = min(args.pauli_samples, B)
+        xp = x[:Bp].contiguous()
+        t0 = time.perf_counter()
+        n_str, n_flip = ham.pauli_build()
+        t_build = time.perf_counter() - t0
+        ep = torch.empty((Bp, 2), dtype=torch.float64, device=dev)
+        es = torch.empty((Bp, 2), dtype=torch.float64, device=dev)
+        ham.eval_pauli(ans16, xp, out=ep)
+        ham.eval(ans16, xp, out=es, want_logpsi=False)
+        torch.cuda.synchronize()
+        ham.timing(True)
+        ham.kernel_time(reset=True)
+        ham.eval_pauli(ans16, xp, out=ep)
+        pms, _ = ham.kernel_time(reset=True)
+        ham.eval(ans16, xp, out=es, want_logpsi=False)
+        sms, _ = ham.kernel_time(reset=True)
+        ham.timing(False)
+        diff = float(((ep - es).norm(dim=1) / es.norm(dim=1)).max().item())
+        out["pauli_route"] = {"samples": Bp, "strings": n_str, "unique_flips": n_flip, "connected": C,
+                              "build_s": t_build, "kernel_ms": pms, "slater_condon_kernel_ms": sms,
+                              "ansatz_rows_ratio": (n_flip - 1) / (C - 1), "time_ratio": pms / sms,
+                              "max_rel_diff_vs_slater_condon": diff}
 
     # --- KPM: Chebyshev moments on a full-sector vector (12 orbitals, 6a+6b); each step is
     # one sector-wide H v (row-by-row generator + Slater--Condon + ranked gathers)

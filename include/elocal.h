@@ -185,6 +185,30 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s,
                                 double* const* logpsi);
 
 /*
+ * The paper's own local-energy route (Results, local-energy equation over Pauli strings,
+ * Algorithm 1 and the Pauli-element equation; Methods, Jordan--Wigner map): H is
+ * rewritten as real-coefficient Pauli strings c X^m Z^z (on every qubit X before Z,
+ * Y = i X Z; qubit k = spin-orbital k), grouped by flip mask m (the unique flips of
+ * Algorithm 1, the identity first). E_loc(x) = sum over masks m of
+ * H_m(x) Psi(x XOR m) / Psi(x), H_m(x) = sum over the mask's strings of
+ * c (-1)^|z & (x XOR m)|; a flip that leaves the sector has Psi = 0 and contributes 0.
+ * Every unique flip is run through the ansatz, as in the paper; elocal_eval runs only
+ * the C connected determinants, with the same result.
+ *
+ * elocal_pauli_build: builds the strings from HOST integrals (the same h1e/eri as
+ *   elocal_create; synchronous) and attaches them to the handle (replacing earlier ones).
+ *   Needs 2 n <= 64. Coefficients below 1e-13 of the largest are dropped (cancellations).
+ * elocal_pauli_count: what = 0 number of strings, 1 number of unique flip masks.
+ * elocal_eval_pauli: E_loc [B][2] through the Pauli route (ELOCAL_BF16 / ELOCAL_BF16X3
+ *   only); workspace elocal_pauli_workspace_bytes.
+ */
+elocal_status elocal_pauli_build(elocal_t h, const double* h1e, const double* eri);
+int64_t elocal_pauli_count(elocal_t h, int what);
+size_t elocal_pauli_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B);
+elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x,
+                                int64_t B, void* ws, size_t ws_bytes, double* eloc);
+
+/*
  * Full-sector vectors and the kernel polynomial method (Methods, KPM for absorption
  * spectra; Results, KPM expansion of the dipole correlation function).
  *

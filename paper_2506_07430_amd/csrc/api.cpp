@@ -7,6 +7,9 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <cmath>
+#include <utility>
+#include <unordered_map>
 
 #include "../../include/elocal.h"
 #include "elocal_internal.hpp"
@@ -74,6 +77,12 @@ struct elocal_ctx {
   double* d_K3 = nullptr;
   uint16_t* d_pairs = nullptr;
   uint32_t* d_binom = nullptr;   // C(o, i) for o, i <= 64 (saturated), for full-sector ranks
+  // Jordan--Wigner strings grouped by flip mask (elocal_pauli_build)
+  uint64_t* d_pl_mask = nullptr;
+  uint32_t* d_pl_off = nullptr;
+  uint64_t* d_pl_z = nullptr;
+  double* d_pl_coef = nullptr;
+  int64_t pl_len = 0, pl_strings = 0;
   int64_t sector_dim = -1;       // C(n, n_alpha) C(n, n_beta), -1 when above 2^31 - 1
   uint32_t sector_nb = 0;        // C(n, n_beta)
   int cu_count = 256;
@@ -204,13 +213,14 @@ int64_t grid_cap(const elocal_ctx* h, int waves) {
   return (int64_t)h->cu_count * (32 / waves);
 }
 
-EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B) {
+EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t list_len = -1) {
   EvalPlan p{};
   // BF16: groups of 64 entries (one per lane), 8 per item; FP64: tiles of 16, 16 per item
   p.rows_per_tile = (G.precision == ELOCAL_BF16) ? 64 : 16;
   p.tpi = (G.precision == ELOCAL_BF16) ? 8 : 16;
   if (h->tune_groups > 0) p.tpi = (uint32_t)std::min<int64_t>(h->tune_groups, 1 << 16);
-  const uint64_t rows = h->sys.C - 1;   // the diagonal entry needs no ansatz call
+  // the first list entry (the sample itself) needs no ansatz call
+  const uint64_t rows = (list_len > 0 ? (uint64_t)list_len : (uint64_t)h->sys.C) - 1;
   const uint64_t per_item = (uint64_t)p.rows_per_tile * p.tpi;
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
   p.n_items = (int64_t)p.ips * B;
@@ -412,6 +422,7 @@ elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int
     hipFree(d_eri);
     hipFree(h->d_h1e); hipFree(h->d_S); hipFree(h->d_J2); hipFree(h->d_K2);
     hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs); hipFree(h->d_binom);
+  hipFree(h->d_pl_mask); hipFree(h->d_pl_off); hipFree(h->d_pl_z); hipFree(h->d_pl_coef);
     delete h;
     return st;
   };
@@ -455,6 +466,7 @@ elocal_status elocal_destroy(elocal_t h) {
   for (hipEvent_t e : h->ev_stop) hipEventDestroy(e);
   hipFree(h->d_h1e); hipFree(h->d_S); hipFree(h->d_J2); hipFree(h->d_K2);
   hipFree(h->d_J3); hipFree(h->d_K3); hipFree(h->d_pairs); hipFree(h->d_binom);
+  hipFree(h->d_pl_mask); hipFree(h->d_pl_off); hipFree(h->d_pl_z); hipFree(h->d_pl_coef);
   delete h;
   return ELOCAL_OK;
 }
@@ -709,6 +721,187 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
   }
   for (int i = 0; i < n_sys; ++i)
     if (B[i] > 0) HIP_TRY(launch_reduce(W[i].ediag, W[i].partial, B[i], M.p[i].ips, eloc[i], st), "reduce launch");
+  return ELOCAL_OK;
+}
+
+// ----------------------------------------------------------------------------- Pauli strings
+namespace {
+
+// A Pauli string on 2n <= 64 qubits as c X^x Z^z (on every qubit X before Z), so that
+// (X^x1 Z^z1)(X^x2 Z^z2) = (-1)^|z1 & x2| X^(x1^x2) Z^(z1^z2). With Y = i X Z the
+// ladder operators of the Jordan--Wigner map are real:
+//   a+_j = Z_{<j} (X_j - i Y_j) / 2 = (X_j + X_j Z_j) Z_{<j} / 2,
+//   a_j  = Z_{<j} (X_j + i Y_j) / 2 = (X_j - X_j Z_j) Z_{<j} / 2.
+struct PTerm {
+  double c;
+  uint64_t x, z;
+};
+
+void ladder(int j, bool dagger, PTerm out[2]) {
+  const uint64_t e = 1ull << j, zs = e - 1;
+  out[0] = {0.5, e, zs};
+  out[1] = {dagger ? 0.5 : -0.5, e, zs | e};
+}
+
+struct KeyHash {
+  size_t operator()(const std::pair<uint64_t, uint64_t>& k) const {
+    return std::hash<uint64_t>()(k.first * 0x9E3779B97F4A7C15ull ^ (k.second + 0x632BE59BD9B4E019ull));
+  }
+};
+
+// coefficient map of sum_ops coef * (product of the ladder operators), accumulated
+void add_product(std::unordered_map<std::pair<uint64_t, uint64_t>, double, KeyHash>& acc, double coef,
+                 const int* modes, const bool* dag, int k) {
+  PTerm terms[16];
+  int nt = 1;
+  terms[0] = {coef, 0, 0};
+  for (int o = 0; o < k; ++o) {
+    PTerm l[2];
+    ladder(modes[o], dag[o], l);
+    PTerm next[16];
+    int m = 0;
+    for (int a = 0; a < nt; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int sgn = (__builtin_popcountll(terms[a].z & l[b].x) & 1) ? -1 : 1;
+        next[m++] = {terms[a].c * l[b].c * sgn, terms[a].x ^ l[b].x, terms[a].z ^ l[b].z};
+      }
+    nt = m;
+    for (int a = 0; a < nt; ++a) terms[a] = next[a];
+  }
+  for (int a = 0; a < nt; ++a) acc[{terms[a].x, terms[a].z}] += terms[a].c;
+}
+
+}  // namespace
+
+elocal_status elocal_pauli_build(elocal_t h, const double* h1e, const double* eri) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (!h1e || !eri) return fail(ELOCAL_E_INVALID, "h1e or eri is null");
+  const int n = h->sys.n;
+  if (2 * n > 64) return fail(ELOCAL_E_UNSUPPORTED, "the Pauli route needs 2 n <= 64 (n=%d)", n);
+  if (elocal_status st = check_device(h)) return st;
+  std::unordered_map<std::pair<uint64_t, uint64_t>, double, KeyHash> acc;
+  acc.reserve(1 << 20);
+  const size_t N = n;
+  for (int s = 0; s < 2; ++s)
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        const double v = h1e[p * N + q];
+        if (v == 0.0) continue;
+        const int modes[2] = {2 * p + s, 2 * q + s};
+        const bool dag[2] = {true, false};
+        add_product(acc, v, modes, dag, 2);
+      }
+  // 1/2 sum (pq|rs) a+_{ps} a+_{rt} a_{st} a_{qs}
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t)
+      for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+          for (int r = 0; r < n; ++r)
+            for (int u = 0; u < n; ++u) {
+              const double v = eri[((p * N + q) * N + r) * N + u];
+              const int P = 2 * p + s, R = 2 * r + t, U = 2 * u + t, Q = 2 * q + s;
+              if (v == 0.0 || P == R || U == Q) continue;   // a+_P a+_P = a_Q a_Q = 0
+              const int modes[4] = {P, R, U, Q};
+              const bool dag[4] = {true, true, false, false};
+              add_product(acc, 0.5 * v, modes, dag, 4);
+            }
+  // drop what cancelled (exactly or to rounding), group by flip mask, identity first
+  double cmax = 0.0;
+  for (const auto& kv : acc) cmax = std::max(cmax, std::fabs(kv.second));
+  std::vector<std::pair<std::pair<uint64_t, uint64_t>, double>> terms;
+  terms.reserve(acc.size());
+  for (const auto& kv : acc)
+    if (std::fabs(kv.second) > 1e-13 * cmax) terms.push_back(kv);
+  std::sort(terms.begin(), terms.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  std::vector<uint64_t> mask, zs;
+  std::vector<uint32_t> off;
+  std::vector<double> coef;
+  mask.push_back(0);
+  off.push_back(0);
+  for (const auto& t : terms) {
+    if (t.first.first != mask.back()) {
+      off.push_back((uint32_t)zs.size());
+      mask.push_back(t.first.first);
+    }
+    zs.push_back(t.first.second);
+    coef.push_back(t.second);
+  }
+  off.push_back((uint32_t)zs.size());
+  if (zs.empty()) {   // keep the device arrays non-empty
+    zs.push_back(0);
+    coef.push_back(0.0);
+  }
+  hipFree(h->d_pl_mask); hipFree(h->d_pl_off); hipFree(h->d_pl_z); hipFree(h->d_pl_coef);
+  h->d_pl_mask = nullptr; h->d_pl_off = nullptr; h->d_pl_z = nullptr; h->d_pl_coef = nullptr;
+  h->pl_len = h->pl_strings = 0;
+  if (hipMalloc(&h->d_pl_mask, mask.size() * 8) != hipSuccess || hipMalloc(&h->d_pl_off, off.size() * 4) != hipSuccess ||
+      hipMalloc(&h->d_pl_z, zs.size() * 8) != hipSuccess || hipMalloc(&h->d_pl_coef, coef.size() * 8) != hipSuccess)
+    return fail(ELOCAL_E_NOMEM, "device allocation failed in elocal_pauli_build");
+  hipError_t e = hipMemcpy(h->d_pl_mask, mask.data(), mask.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_pl_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_pl_z, zs.data(), zs.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_pl_coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "elocal_pauli_build copy");
+  h->pl_len = (int64_t)mask.size();
+  h->pl_strings = (int64_t)terms.size();
+  return ELOCAL_OK;
+}
+
+int64_t elocal_pauli_count(elocal_t h, int what) {
+  if (!h) return -1;
+  return what == 0 ? h->pl_strings : h->pl_len;
+}
+
+size_t elocal_pauli_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B) {
+  if (!h) { fail(ELOCAL_E_INVALID, "handle is null"); return 0; }
+  if (h->pl_len <= 0) { fail(ELOCAL_E_CONFIG, "no Pauli strings: call elocal_pauli_build first"); return 0; }
+  AnsatzGeom G;
+  if (make_geom(h, a, G) != ELOCAL_OK) return 0;
+  const EvalPlan p = plan_eval(h, G, B, h->pl_len);
+  return carve_eval(h, G, p, B, nullptr).bytes;
+}
+
+elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x, int64_t B,
+                                void* ws, size_t ws_bytes, double* eloc) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (h->pl_len <= 0) return fail(ELOCAL_E_CONFIG, "no Pauli strings: call elocal_pauli_build first");
+  AnsatzGeom G;
+  if (elocal_status e = make_geom(h, a, G)) return e;
+  if (G.precision != ELOCAL_BF16) return fail(ELOCAL_E_UNSUPPORTED, "the Pauli route runs the BF16 modes only");
+  if (B < 0) return fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B);
+  if (B == 0) return ELOCAL_OK;
+  if (!a->theta || !x || !ws || !eloc) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  const EvalPlan p = plan_eval(h, G, B, h->pl_len);
+  const EvalWs need = carve_eval(h, G, p, B, nullptr);
+  if (ws_bytes < need.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const EvalWs w = carve_eval(h, G, p, B, ws);
+  hipStream_t st = (hipStream_t)s;
+  MadeDev M = G.md;
+  M.wfrag = w.frag;
+  M.bias = w.bias;
+  HIP_TRY(launch_pack_bf16(M, G.T, (const uint16_t*)a->theta, w.frag, (float*)w.bias, st), "pack launch");
+  HIP_TRY(launch_pauli_diag(x, B, h->d_pl_off, h->d_pl_z, h->d_pl_coef, w.ediag, st), "diagonal launch");
+  RowsArgs R{};
+  R.sys = h->sys; R.made = M; R.x = x; R.B = B; R.lpx = w.lpx; R.zphi = w.zphi; R.logpsi = nullptr;
+  HIP_TRY(launch_rows_bf16(R, G.hmax, G.nterms, st), "sample pass launch");
+  EvalArgs E{};
+  E.sys = h->sys; E.made = M; E.x = x; E.B = B; E.ediag = w.ediag; E.F = w.F; E.lpx = w.lpx; E.zphi = w.zphi;
+  E.partial = w.partial; E.n_items = p.n_items; E.ips = p.ips; E.tpi = p.tpi;
+  E.lds_bias_off = p.ldsw ? (uint32_t)align256(G.wbytes) : 0;
+  E.lds_ctx_off = p.ldsw ? (uint32_t)(align256(G.wbytes) + align256(G.bbytes)) : 0;
+  E.pl_mask = h->d_pl_mask; E.pl_off = h->d_pl_off; E.pl_z = h->d_pl_z; E.pl_coef = h->d_pl_coef;
+  E.pl_len = (uint32_t)h->pl_len;
+  const bool timed = h->timing && p.n_items > 0;
+  const int slot = (int)(h->ring_pos % elocal_ctx::kRing);
+  if (timed) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
+  HIP_TRY(launch_eval_pauli_bf16(E, G.hmax, G.nterms, p.ldsw, p.lds, p.grid, st), "Pauli eval launch");
+  if (timed) {
+    HIP_TRY(hipEventRecord(h->ev_stop[slot], st), "timing event");
+    h->ring_pos++;
+    h->recorded++;
+  }
+  HIP_TRY(launch_reduce(w.ediag, w.partial, B, p.ips, eloc, st), "reduce launch");
   return ELOCAL_OK;
 }
 

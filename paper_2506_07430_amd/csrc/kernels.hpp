@@ -28,6 +28,13 @@ struct EvalArgs {
   uint32_t tpi;            // row tiles per work item
   uint32_t lds_bias_off;   // byte offset of the biases in LDS (weights at 0)
   uint32_t lds_ctx_off;    // byte offset of the per-wave contexts
+  // Pauli-string route only: unique flip masks [pl_len], string offsets [pl_len + 1],
+  // string Z masks and real coefficients [pl_off[pl_len]]
+  const uint64_t* pl_mask;
+  const uint32_t* pl_off;
+  const uint64_t* pl_z;
+  const double* pl_coef;
+  uint32_t pl_len;
 };
 
 // Arguments of the ansatz pass over the samples themselves.
@@ -69,6 +76,11 @@ constexpr int kMaxEvalWavesBF16 = 8;
 // s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax, nterms) work items each (LDS layout as
 // for one system: weights at 0, biases at bias_off, wave contexts at ctx_off). FP64:
 // system s owns work items [first[s], first[s+1]).
+hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, size_t lds_bytes,
+                                  unsigned grid, hipStream_t st);
+// Pauli route, diagonal (identity-flip) group: ediag[b] = sum_k c_k (-1)^|z_k & x_b|.
+hipError_t launch_pauli_diag(const uint64_t* x, int64_t B, const uint32_t* off, const uint64_t* z,
+                             const double* coef, double* ediag, hipStream_t st);
 hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
                                   bool ldsw, size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid,
                                   hipStream_t st);

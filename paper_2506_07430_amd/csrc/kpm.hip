@@ -200,7 +200,27 @@ __global__ void k_line_shape(const double* __restrict__ mu, int64_t N, const dou
   rho[j] = s / (M_PI * sqrt(1.0 - x * x));
 }
 
+// Pauli-string route: the identity-flip group (diagonal strings) of every sample,
+// ediag[b] = sum_k c_k (-1)^|z_k & x_b| in string order; one thread per sample.
+__global__ void k_pauli_diag(const uint64_t* __restrict__ x, int64_t B, const uint32_t* __restrict__ off,
+                             const uint64_t* __restrict__ z, const double* __restrict__ coef,
+                             double* __restrict__ ediag) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const uint64_t xb = x[b];
+  double h = 0.0;
+  for (uint32_t k = off[0], e = off[1]; k < e; ++k) h += (__popcll(z[k] & xb) & 1) ? -coef[k] : coef[k];
+  ediag[b] = h;
+}
+
 // ----------------------------------------------------------------------------- launchers
+hipError_t launch_pauli_diag(const uint64_t* x, int64_t B, const uint32_t* off, const uint64_t* z,
+                             const double* coef, double* ediag, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pauli_diag, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, x, B, off, z, coef, ediag);
+  return hipGetLastError();
+}
+
 hipError_t launch_sector_apply(const SysDev& S, const uint32_t* binom, int64_t dim, uint32_t nb_dim, double ch,
                                double cv, const double* v, double cz, const double* z, double* y, double* partial,
                                unsigned grid, hipStream_t st) {

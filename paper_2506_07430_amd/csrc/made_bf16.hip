@@ -447,7 +447,47 @@ struct SampleState {
 // every lane generates one entry (x', H_{x'x} in FP64, first changed orbital); the
 // network runs twice on 32 of them; every lane then forms H exp(dA + i dphi) in FP64
 // for its own entry. The item's partial sum (fixed order) goes to P.partial[item].
-template <int HMAX, int NW, int NT>
+// Entry generators of the fused kernel. Entry t of a sample's list (t = 0 is the sample
+// itself and is handled outside the kernel) gives x' and H_{x x'}.
+//
+// Slater--Condon route: the canonical list of single and double excitations.
+struct ScGen {
+  __device__ __forceinline__ static uint32_t length(const EvalArgs& P) { return P.sys.C; }
+  template <int NW>
+  __device__ __forceinline__ static double entry(const EvalArgs& P, const SampleCtx& c, const uint64_t (&xs)[NW],
+                                                 const double* Fs, double ed, uint32_t t, uint64_t (&xo)[NW]) {
+    const Excitation e = unrank(P.sys, c, t);
+    const int sg = apply_excitation<NW>(xs, e, xo);
+    const double v = excitation_value(P.sys, e, Fs, ed);
+    return sg < 0 ? -v : v;
+  }
+};
+
+// Pauli-string route (Results, Algorithm 1): entry t is unique flip mask t; x' = x XOR
+// mask and H_{x x'} = sum over the strings c X^mask Z^z of that mask of c (-1)^|z & x'|.
+// A flip that leaves the (n_alpha, n_beta) sector gets H = 0 exactly (there the ansatz is
+// zero; its strings' coefficients cancel up to rounding).
+struct PauliGen {
+  __device__ __forceinline__ static uint32_t length(const EvalArgs& P) { return P.pl_len; }
+  template <int NW>
+  __device__ __forceinline__ static double entry(const EvalArgs& P, const SampleCtx&, const uint64_t (&xs)[NW],
+                                                 const double*, double, uint32_t t, uint64_t (&xo)[NW]) {
+    const uint64_t m = P.pl_mask[t];
+    xo[0] = xs[0] ^ m;
+#pragma unroll
+    for (int w = 1; w < NW; ++w) xo[w] = xs[w];
+    const uint64_t A = 0x5555555555555555ull;
+    if (__popcll(xo[0] & A) != __popcll(xs[0] & A) || __popcll(xo[0] & ~A) != __popcll(xs[0] & ~A)) return 0.0;
+    double h = 0.0;
+    for (uint32_t k = P.pl_off[t], e = P.pl_off[t + 1]; k < e; ++k) {
+      const double c = P.pl_coef[k];
+      h += (__popcll(P.pl_z[k] & xo[0]) & 1) ? -c : c;
+    }
+    return h;
+  }
+};
+
+template <int HMAX, int NW, int NT, class Gen = ScGen>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* __restrict__ W,
                                                const float* __restrict__ bias, WaveCtxBF16& wc,
                                                int64_t item, SampleState<NW>& st, int lane) {
@@ -471,19 +511,17 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
     st.b = b;
   }
   const uint64_t(&xs)[NW] = st.xs;
+  const uint32_t len = Gen::length(P);
   double acc_re = 0.0, acc_im = 0.0;
   for (uint32_t grp = 0; grp < P.tpi; ++grp) {
     const uint32_t t0 = 1u + (seg * P.tpi + grp) * 64u;
-    if (t0 >= S.C) break;
+    if (t0 >= len) break;
     // ---- generate this lane's entry
     const uint32_t t = t0 + lane;
     uint64_t xo[NW];
     double hv = 0.0;
-    if (t < S.C) {
-      const Excitation e = unrank(S, wc.c, t);
-      const int sg = apply_excitation<NW>(xs, e, xo);
-      const double v = excitation_value(S, e, st.Fs, st.ed);
-      hv = sg < 0 ? -v : v;
+    if (t < len) {
+      hv = Gen::template entry<NW>(P, wc.c, xs, st.Fs, st.ed, t, xo);
     } else {
 #pragma unroll
       for (int w = 0; w < NW; ++w) xo[w] = xs[w];
@@ -534,8 +572,9 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
         zp_own = c ? zp[1] : zp[0];
       }
     }
-    // ---- FP64 ratio and accumulation, one entry per lane
-    if (t < S.C) {
+    // ---- FP64 ratio and accumulation, one entry per lane (an entry with H = 0 adds
+    // nothing; skipping it also keeps an infinite ratio of a zero-amplitude x' out)
+    if (t < len && hv != 0.0) {
       // phase difference 2 pi d with |d| < 1: sincospi needs no large-argument reduction;
       // the magnitude exp(dA ln2 / 2) with dA in log2 units is exp2(dA / 2)
       const double d = 1.0 / (1.0 + exp(-(double)zp_own)) - st.sig_x;
@@ -590,6 +629,29 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
     eval_item_bf16<HMAX, NW, NT>(P, W, bias, wc, item, st, lane);
+}
+
+// Pauli-string route: the fused kernel over the unique flip masks of every sample (one
+// word per determinant: n <= 32).
+template <int HMAX, int NT, bool LDSW>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_pauli_bf16(EvalArgs P) {
+  constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
+  const bf16x8* W = (const bf16x8*)P.made.wfrag;
+  const float* bias = (const float*)P.made.bias;
+  if (LDSW) {
+    stage_weights(P.made, smem, P.lds_bias_off);
+    __syncthreads();
+    W = (const bf16x8*)smem;
+    bias = (const float*)(smem + P.lds_bias_off);
+  }
+  WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + P.lds_ctx_off))[wid];
+  SampleState<1> st;
+  st.b = -1;
+  for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
+       item += (int64_t)gridDim.x * kEvalWaves)
+    eval_item_bf16<HMAX, 1, NT, PauliGen>(P, W, bias, wc, item, st, lane);
 }
 
 // Several systems in one persistent launch. Work is cut into chunks of kEvalWaves items
@@ -702,6 +764,22 @@ hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, 
     };
     if (A.sys.W == 1) return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true>) : go(k_eval_bf16<HMAX, 1, NT, false>);
     return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true>) : go(k_eval_bf16<HMAX, 2, NT, false>);
+  });
+}
+
+hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, size_t lds, unsigned grid,
+                                  hipStream_t st) {
+  if (A.n_items <= 0) return hipSuccess;
+  if (A.sys.W != 1) return hipErrorInvalidValue;
+  return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
+    constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
+    auto go = [&](auto kern) {
+      hipError_t e = allow_lds(kern, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, A);
+      return hipGetLastError();
+    };
+    return ldsw ? go(k_eval_pauli_bf16<HMAX, NT, true>) : go(k_eval_pauli_bf16<HMAX, NT, false>);
   });
 }
 

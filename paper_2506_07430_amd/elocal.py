@@ -67,6 +67,12 @@ def lib():
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
         L.elocal_tune.argtypes = [vp, i32, i64]
+        L.elocal_pauli_build.argtypes = [vp, vp, vp]
+        L.elocal_pauli_count.argtypes = [vp, i32]
+        L.elocal_pauli_count.restype = i64
+        L.elocal_pauli_workspace_bytes.argtypes = [vp, P(_Ansatz), i64]
+        L.elocal_pauli_workspace_bytes.restype = sz
+        L.elocal_eval_pauli.argtypes = [vp, vp, P(_Ansatz), vp, i64, vp, sz, vp]
         L.elocal_sector_dim.argtypes = [vp]
         L.elocal_sector_dim.restype = i64
         L.elocal_sector_workspace_bytes.argtypes = [vp, i32]
@@ -82,7 +88,7 @@ def lib():
         for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
                   "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune",
                   "elocal_eval_multi", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
-                  "elocal_kpm_line_shape"):
+                  "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_eval_pauli"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -94,7 +100,8 @@ def exported_symbols() -> Sequence[str]:
             "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune", "elocal_last_error",
             "elocal_workspace_bytes_multi", "elocal_eval_multi", "elocal_sector_dim",
             "elocal_sector_workspace_bytes", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
-            "elocal_kpm_line_shape"]
+            "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_pauli_count", "elocal_pauli_workspace_bytes",
+            "elocal_eval_pauli"]
 
 
 def _check(status: int):
@@ -155,6 +162,7 @@ class Hamiltonian:
         self.C = int(lib().elocal_num_connected(h))
         self.W = int(lib().elocal_words(h))
         self._ws = {}
+        self._h1e, self._eri = h1e, eri
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     def close(self):
@@ -257,6 +265,28 @@ class Hamiltonian:
         """Launch shape of the fused kernel (0 = built-in)."""
         _check(lib().elocal_tune(self._h, 0, int(grid)))
         _check(lib().elocal_tune(self._h, 1, int(groups)))
+
+    # ------------------------------------------------------------------ Pauli-string route
+    def pauli_build(self):
+        """Jordan--Wigner strings of this Hamiltonian, grouped by flip mask (host, synchronous)."""
+        _check(lib().elocal_pauli_build(self._h, self._h1e.ctypes.data, self._eri.ctypes.data))
+        return int(lib().elocal_pauli_count(self._h, 0)), int(lib().elocal_pauli_count(self._h, 1))
+
+    def eval_pauli(self, ansatz: Ansatz, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        """E_loc [B, 2] through the Pauli-string route (after pauli_build)."""
+        x = self._x(x)
+        B = x.shape[0]
+        eloc = out if out is not None else torch.empty((B, 2), dtype=torch.float64, device=x.device)
+        need = int(lib().elocal_pauli_workspace_bytes(self._h, ansatz.ref(), B))
+        if need == 0:
+            raise ElocalError(2, lib().elocal_last_error().decode())
+        buf = self._ws.get("pauli")
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws["pauli"] = buf
+        _check(lib().elocal_eval_pauli(self._h, _stream(stream), ansatz.ref(), x.data_ptr(), B, buf.data_ptr(),
+                                       buf.numel(), eloc.data_ptr()))
+        return eloc
 
     # ------------------------------------------------------------------ full sector / KPM
     @property
