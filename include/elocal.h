@@ -185,6 +185,23 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s,
                                 double* const* logpsi);
 
 /*
+ * Local energies with every distinct connected determinant of the batch evaluated once
+ * (the paper's deduplication of coupled configurations before the forward pass). The
+ * lists are materialised (as elocal_connect), their determinants inserted into a hash
+ * table, the ansatz run once per distinct determinant, and each E_loc assembled over
+ * its list in canonical order. Same outputs as elocal_eval up to rounding (here A' - A
+ * is a difference of totals). Worth it when the sector is small next to B x C (e.g. 8
+ * orbitals: 369,664 list entries over at most 4,900 determinants); for large sectors
+ * it only adds the materialisation. Needs n <= 32 and B x C < 2^32.
+ * n_distinct (device, may be NULL) receives the number of distinct determinants.
+ * Workspace: elocal_dedup_workspace_bytes (about 60 bytes per list entry).
+ */
+size_t elocal_dedup_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B);
+elocal_status elocal_eval_dedup(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x,
+                                int64_t B, void* ws, size_t ws_bytes, double* eloc, double* logpsi,
+                                int64_t* n_distinct);
+
+/*
  * The paper's own local-energy route (Results, local-energy equation over Pauli strings,
  * Algorithm 1 and the Pauli-element equation; Methods, Jordan--Wigner map): H is
  * rewritten as real-coefficient Pauli strings c X^m Z^z (on every qubit X before Z,

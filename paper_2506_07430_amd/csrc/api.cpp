@@ -204,8 +204,8 @@ struct EvalPlan {
 };
 
 constexpr size_t kLdsBytes = 160 * 1024;
-// per-wave LDS context of the BF16 kernel: occupied/virtual lists + log2 p of the sample
-constexpr size_t kCtxBytesBF16 = kMaxEvalWavesBF16 * (sizeof(SampleCtx) + kMaxOrb * sizeof(float));
+// per-wave LDS contexts of the BF16 kernel (every wave of a block)
+constexpr size_t kCtxBytesBF16 = kMaxEvalWavesBF16 * kWaveCtxBytesBF16;
 
 // Persistent grid: 32 waves per CU in total (a few rounds of resident blocks), unless tuned.
 int64_t grid_cap(const elocal_ctx* h, int waves) {
@@ -902,6 +902,107 @@ elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz
     h->recorded++;
   }
   HIP_TRY(launch_reduce(w.ediag, w.partial, B, p.ips, eloc, st), "reduce launch");
+  return ELOCAL_OK;
+}
+
+// ----------------------------------------------------------------------------- deduplicated eval
+namespace {
+
+struct DedupWs {
+  double* ediag;
+  double* F;
+  void* frag;
+  void* bias;
+  uint64_t* xp;
+  double* hval;
+  int8_t* sign;
+  uint32_t* exc;
+  uint64_t* keys;
+  uint32_t* ids;
+  uint64_t* unique;
+  float* lpx;
+  double* lpx64;
+  double* zphi;
+  double* logpsi_u;
+  int64_t* counters;
+  uint64_t nslots;
+  size_t bytes;
+};
+
+DedupWs carve_dedup(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, void* ws) {
+  Carve c(ws);
+  DedupWs w{};
+  const size_t Bs = (size_t)std::max<int64_t>(B, 1), total = Bs * h->sys.C;
+  const size_t nS = h->sys.nSa + h->sys.nSb;
+  uint64_t ns = 1024;
+  while (ns < 2 * total) ns <<= 1;
+  w.nslots = ns;
+  w.ediag = c.take<double>(Bs);
+  w.F = c.take<double>(std::max<size_t>(Bs * nS, 1));
+  w.frag = c.take<char>(G.wbytes);
+  w.bias = c.take<char>(G.bbytes);
+  w.xp = c.take<uint64_t>(total);
+  w.hval = c.take<double>(total);
+  w.sign = c.take<int8_t>(total);
+  w.exc = c.take<uint32_t>(total);
+  w.keys = c.take<uint64_t>(ns);
+  w.ids = c.take<uint32_t>(ns);
+  w.unique = c.take<uint64_t>(total);
+  if (G.precision == ELOCAL_BF16) w.lpx = c.take<float>(total * h->sys.n);
+  else w.lpx64 = c.take<double>(total * h->sys.n);
+  w.zphi = c.take<double>(total);
+  w.logpsi_u = c.take<double>(2 * total);
+  w.counters = c.take<int64_t>(2);
+  w.bytes = c.off;
+  return w;
+}
+
+}  // namespace
+
+size_t elocal_dedup_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B) {
+  if (!h) { fail(ELOCAL_E_INVALID, "handle is null"); return 0; }
+  AnsatzGeom G;
+  if (make_geom(h, a, G) != ELOCAL_OK) return 0;
+  return carve_dedup(h, G, B, nullptr).bytes;
+}
+
+elocal_status elocal_eval_dedup(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x, int64_t B,
+                                void* ws, size_t ws_bytes, double* eloc, double* logpsi, int64_t* n_distinct) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (h->sys.W != 1) return fail(ELOCAL_E_UNSUPPORTED, "deduplication needs one word per determinant (n <= 32)");
+  AnsatzGeom G;
+  if (elocal_status e = make_geom(h, a, G)) return e;
+  if (B < 0) return fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B);
+  if (B == 0) return ELOCAL_OK;
+  if (!a->theta || !x || !ws || !eloc) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  if ((uint64_t)B * h->sys.C > 0xFFFFFFFFull) return fail(ELOCAL_E_UNSUPPORTED, "B x C exceeds 2^32 list entries");
+  const DedupWs need = carve_dedup(h, G, B, nullptr);
+  if (ws_bytes < need.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const DedupWs w = carve_dedup(h, G, B, ws);
+  hipStream_t st = (hipStream_t)s;
+  const int64_t total = B * (int64_t)h->sys.C;
+  MadeDev M = G.md;
+  M.wfrag = w.frag;
+  M.bias = w.bias;
+  if (G.precision == ELOCAL_BF16)
+    HIP_TRY(launch_pack_bf16(M, G.T, (const uint16_t*)a->theta, w.frag, (float*)w.bias, st), "pack launch");
+  else
+    HIP_TRY(launch_pack_f64(M, G.T, (const double*)a->theta, w.frag, (double*)w.bias, st), "pack launch");
+  HIP_TRY(launch_prep(h->sys, x, B, w.ediag, w.F, st), "prep launch");
+  HIP_TRY(launch_connect(h->sys, x, B, w.ediag, w.F, w.xp, w.hval, w.sign, w.exc, st), "connect launch");
+  HIP_TRY(launch_dd_clear(w.keys, w.nslots, w.counters, st), "table clear launch");
+  HIP_TRY(launch_dd_insert(w.xp, total, w.keys, w.nslots - 1, w.counters, st), "table insert launch");
+  HIP_TRY(launch_dd_compact(w.keys, w.nslots, w.ids, w.unique, w.counters, st), "compaction launch");
+  RowsArgs R{};
+  R.sys = h->sys; R.made = M; R.x = w.unique; R.B = total; R.lpx = w.lpx; R.lpx64 = w.lpx64; R.zphi = w.zphi;
+  R.logpsi = w.logpsi_u; R.count = w.counters;
+  if (G.precision == ELOCAL_BF16) HIP_TRY(launch_rows_bf16(R, G.hmax, G.nterms, st), "distinct rows launch");
+  else HIP_TRY(launch_rows_f64(R, G.hmax, st), "distinct rows launch");
+  HIP_TRY(launch_dd_assemble(w.xp, w.hval, B, h->sys.C, w.keys, w.ids, w.nslots - 1, w.logpsi_u, eloc, logpsi,
+                             w.counters, st), "assemble launch");
+  if (n_distinct)
+    HIP_TRY(hipMemcpyAsync(n_distinct, w.counters, sizeof(int64_t), hipMemcpyDeviceToDevice, st), "count copy");
   return ELOCAL_OK;
 }
 

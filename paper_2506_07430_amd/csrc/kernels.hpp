@@ -47,6 +47,7 @@ struct RowsArgs {
   double* lpx64;           // [B][n] (FP64 mode)
   double* zphi;            // [B]
   double* logpsi;          // [B][2] or null
+  const int64_t* count;    // if not null: only rows < min(B, *count) are evaluated (device count)
 };
 
 hipError_t launch_build_tables(int n, const double* eri, double* S, double* J2, double* K2,
@@ -72,6 +73,9 @@ hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_we
 // this layer's and the next) fit in 256 registers, else one (with 512 registers).
 constexpr int eval_waves_bf16(int hmax, int nterms) { return hmax * nterms <= 256 ? 8 : 4; }
 constexpr int kMaxEvalWavesBF16 = 8;
+// Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists and
+// the FP64 suffix sums of its per-orbital log2 probabilities.
+constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(double);
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system
 // s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax, nterms) work items each (LDS layout as
 // for one system: weights at 0, biases at bias_off, wave contexts at ctx_off). FP64:
@@ -109,6 +113,16 @@ hipError_t launch_norm2(const double* v, int64_t dim, double* out, hipStream_t s
 hipError_t launch_sector_basis(const SysDev& S, const uint32_t* binom, int64_t dim, uint32_t nb_dim, uint64_t* x,
                                hipStream_t st);
 hipError_t launch_line_shape(const double* mu, int64_t N, const double* w, int64_t P, double* rho, hipStream_t st);
+
+// Batch-level deduplication of the connected determinants (one word per determinant).
+hipError_t launch_dd_clear(uint64_t* keys, uint64_t nslots, int64_t* counters, hipStream_t st);
+hipError_t launch_dd_insert(const uint64_t* xp, int64_t total, uint64_t* keys, uint64_t mask, int64_t* counters,
+                            hipStream_t st);
+hipError_t launch_dd_compact(const uint64_t* keys, uint64_t nslots, uint32_t* ids, uint64_t* unique, int64_t* counters,
+                             hipStream_t st);
+hipError_t launch_dd_assemble(const uint64_t* xp, const double* hval, int64_t B, uint32_t C, const uint64_t* keys,
+                              const uint32_t* ids, uint64_t mask, const double* logpsi_u, double* eloc,
+                              double* logpsi_out, int64_t* counters, hipStream_t st);
 
 // Statistics and gradient (FP64).
 hipError_t launch_stats(const double* eloc, const double* w, int64_t B, double* stats, hipStream_t st);

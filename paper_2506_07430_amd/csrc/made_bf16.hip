@@ -378,7 +378,8 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t b0 = wave * 32;
-  if (b0 >= P.B) return;
+  const int64_t Bn = P.count ? min(P.B, *P.count) : P.B;
+  if (b0 >= Bn) return;
   const MadeDev& M = P.made;
   const int n = P.sys.n, na = P.sys.na, nb = P.sys.nb;
   const bf16x8* W = (const bf16x8*)M.wfrag;
@@ -388,7 +389,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     rb[c] = b0 + 16 * c + r16;
-    const int64_t bb = rb[c] < P.B ? rb[c] : b0;
+    const int64_t bb = rb[c] < Bn ? rb[c] : b0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) xr[c][w] = P.x[bb * NW + w];
   }
@@ -404,7 +405,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
       for (int c = 0; c < 2; ++c) {
         const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
         A[c] += (double)lp;
-        if (rb[c] < P.B) P.lpx[rb[c] * n + p] = lp;     // log2 units
+        if (rb[c] < Bn) P.lpx[rb[c] * n + p] = lp;     // log2 units
       }
     }
     if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
@@ -417,7 +418,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   }
   if (g < 2) {
     const int c = g;
-    if (rb[c] < P.B) {
+    if (rb[c] < Bn) {
       P.zphi[rb[c]] = (double)zp[c];
       if (P.logpsi) {
         const double sig = 1.0 / (1.0 + exp(-(double)zp[c]));
@@ -431,8 +432,9 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
 // ----------------------------------------------------------------------------- fused eval
 struct WaveCtxBF16 {
   SampleCtx c;
-  float lpx[kMaxOrb];   // log2 p_p(s_p) of the sample
+  double sfx[kMaxOrb + 1];   // sum_{q >= p} log2 p_q(s_q) of the sample, sfx[n] = 0
 };
+static_assert(sizeof(WaveCtxBF16) == kWaveCtxBytesBF16, "per-wave LDS context size");
 
 // What a wave keeps of the sample its current work item belongs to.
 template <int NW>
@@ -503,7 +505,17 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
 #pragma unroll
     for (int w = 0; w < NW; ++w) st.xs[w] = P.x[b * NW + w];
     build_ctx<NW>(S, st.xs, wc.c, lane);
-    if (lane < n) wc.lpx[lane] = P.lpx[b * n + lane];
+    {
+      // suffix sums of the sample's log2 p in FP64 (a fixed shuffle tree)
+      double v = lane < n ? (double)P.lpx[b * n + lane] : 0.0;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_down(v, off);
+        if (lane + off < 64) v += u;
+      }
+      if (lane < n) wc.sfx[lane] = v;
+      if (lane == 0) wc.sfx[n] = 0.0;
+    }
     wave_sync_lds();
     st.sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
     st.ed = P.ediag[b];
@@ -549,13 +561,12 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
         const int p = 4 * ob + g;
         if (p < n) {
-          const float lx = wc.lpx[p];
           const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
-            const float d = p >= p0[c] ? lp - lx : 0.f;
-            dA[c] += (double)d;
+            const float d = p >= p0[c] ? lp : 0.f;
+            dA[c] += (double)d;     // sum over p >= p0 of log2 p(x'); x's part is subtracted below
           }
         }
         if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
@@ -568,7 +579,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       }
       if ((lane >> 5) == h) {
         const int c = (lane >> 4) & 1;
-        dA_own = c ? dA[1] : dA[0];
+        dA_own = (c ? dA[1] : dA[0]) - wc.sfx[p0o];
         zp_own = c ? zp[1] : zp[0];
       }
     }

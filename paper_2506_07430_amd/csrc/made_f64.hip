@@ -155,11 +155,12 @@ __global__ void __launch_bounds__(256) k_rows_f64(RowsArgs P) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t b0 = wave * 16;
-  if (b0 >= P.B) return;
+  const int64_t Bn = P.count ? min(P.B, *P.count) : P.B;
+  if (b0 >= Bn) return;
   const MadeDev& M = P.made;
   const int n = P.sys.n, na = P.sys.na, nb = P.sys.nb;
   const int64_t rb = b0 + r16;
-  const int64_t bb = rb < P.B ? rb : b0;
+  const int64_t bb = rb < Bn ? rb : b0;
   uint64_t xr[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) xr[w] = P.x[bb * NW + w];
@@ -171,14 +172,14 @@ __global__ void __launch_bounds__(256) k_rows_f64(RowsArgs P) {
                       if (p < n) {
                         const double lp = cond_logp64<NW>(xr, p, n, na, nb, a);
                         A += lp;
-                        if (rb < P.B) P.lpx64[rb * n + p] = lp;
+                        if (rb < Bn) P.lpx64[rb * n + p] = lp;
                       }
                       if (ob == ob_phi && g == g_phi) zp = a[0];
                     });
   A += __shfl_xor(A, 16);
   A += __shfl_xor(A, 32);
   zp = __shfl(zp, g_phi * 16 + r16);
-  if (g == 0 && rb < P.B) {
+  if (g == 0 && rb < Bn) {
     P.zphi[rb] = zp;
     if (P.logpsi) {
       P.logpsi[2 * rb] = 0.5 * A;

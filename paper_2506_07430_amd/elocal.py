@@ -67,6 +67,9 @@ def lib():
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
         L.elocal_tune.argtypes = [vp, i32, i64]
+        L.elocal_dedup_workspace_bytes.argtypes = [vp, P(_Ansatz), i64]
+        L.elocal_dedup_workspace_bytes.restype = sz
+        L.elocal_eval_dedup.argtypes = [vp, vp, P(_Ansatz), vp, i64, vp, sz, vp, vp, vp]
         L.elocal_pauli_build.argtypes = [vp, vp, vp]
         L.elocal_pauli_count.argtypes = [vp, i32]
         L.elocal_pauli_count.restype = i64
@@ -88,7 +91,7 @@ def lib():
         for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
                   "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune",
                   "elocal_eval_multi", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
-                  "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_eval_pauli"):
+                  "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_eval_pauli", "elocal_eval_dedup"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -101,7 +104,7 @@ def exported_symbols() -> Sequence[str]:
             "elocal_workspace_bytes_multi", "elocal_eval_multi", "elocal_sector_dim",
             "elocal_sector_workspace_bytes", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
             "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_pauli_count", "elocal_pauli_workspace_bytes",
-            "elocal_eval_pauli"]
+            "elocal_eval_pauli", "elocal_dedup_workspace_bytes", "elocal_eval_dedup"]
 
 
 def _check(status: int):
@@ -265,6 +268,26 @@ class Hamiltonian:
         """Launch shape of the fused kernel (0 = built-in)."""
         _check(lib().elocal_tune(self._h, 0, int(grid)))
         _check(lib().elocal_tune(self._h, 1, int(groups)))
+
+    # ------------------------------------------------------------------ deduplicated eval
+    def eval_dedup(self, ansatz: Ansatz, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   want_logpsi: bool = False, stream=None):
+        """(eloc [B, 2], logpsi [B, 2] or None, distinct-determinant count (device int64 [1]))."""
+        x = self._x(x)
+        B = x.shape[0]
+        eloc = out if out is not None else torch.empty((B, 2), dtype=torch.float64, device=x.device)
+        lp = torch.empty((B, 2), dtype=torch.float64, device=x.device) if want_logpsi else None
+        cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
+        need = int(lib().elocal_dedup_workspace_bytes(self._h, ansatz.ref(), B))
+        if need == 0:
+            raise ElocalError(1, lib().elocal_last_error().decode())
+        buf = self._ws.get("dedup")
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws["dedup"] = buf
+        _check(lib().elocal_eval_dedup(self._h, _stream(stream), ansatz.ref(), x.data_ptr(), B, buf.data_ptr(),
+                                       buf.numel(), eloc.data_ptr(), _ptr(lp), cnt.data_ptr()))
+        return eloc, lp, cnt
 
     # ------------------------------------------------------------------ Pauli-string route
     def pauli_build(self):
