@@ -36,7 +36,8 @@
  *   caller's workspace). elocal_create copies the integrals (host pointers) to device
  *   memory owned by the handle.
  * Streams: compute calls only enqueue work on the given stream (NULL = the default
- *   stream) and return; they never synchronise, except elocal_check_samples.
+ *   stream) and return; they never synchronise, except elocal_check_samples and
+ *   elocal_sample.
  * Errors: every call returns elocal_status; a non-zero status leaves the outputs
  *   unspecified and the handle usable. elocal_last_error() gives a message for the
  *   calling thread's last failure.
@@ -183,6 +184,27 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s,
                                 const elocal_ansatz* const* a, const uint64_t* const* x,
                                 const int64_t* B, void* ws, size_t ws_bytes, double* const* eloc,
                                 double* const* logpsi);
+
+/*
+ * Batch autoregressive sampling (Results, parallel sampling: the BAS tree of unique
+ * prefixes with multiplicities, pruned at every orbital, under the number-conserving
+ * conditionals). Draws n_samples in [1, 2^32) determinants from |Psi|^2 and returns them as
+ * *n_unique distinct determinants x_out [*n_unique][W] with counts counts_out [*n_unique]
+ * (device buffers of max_unique entries), in tree order (prefix, then state 0 = empty,
+ * 1 = alpha, 2 = beta, 3 = both). At orbital k every prefix i with weight w splits it by w
+ * independent categorical draws: draw j uses u = (first 53 bits of words 0-1 of
+ * Philox4x32-10 at counter (j, i, k, 0), key (seed low, seed high)) * 2^-53 and takes the
+ * first reachable state whose running probability sum exceeds u (else the last reachable
+ * one). The ansatz is evaluated in FP64 (ELOCAL_FP64 only), so the draws are reproducible.
+ * Synchronous (the tree size is read back at every orbital); ELOCAL_E_WORKSPACE if some
+ * orbital has more than max_unique distinct prefixes. Workspace:
+ * elocal_sample_workspace_bytes. Cost: n orbital steps, each an ansatz pass over the
+ * distinct prefixes and n_samples categorical draws.
+ */
+size_t elocal_sample_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t max_unique);
+elocal_status elocal_sample(elocal_t h, elocal_stream s, const elocal_ansatz* a, int64_t n_samples,
+                            uint64_t seed, int64_t max_unique, void* ws, size_t ws_bytes, uint64_t* x_out,
+                            int64_t* counts_out, int64_t* n_unique);
 
 /*
  * Local energies with every distinct connected determinant of the batch evaluated once

@@ -17,7 +17,7 @@ OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libelocal.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hamiltonian.hip", "made_bf16.hip", "made_f64.hip", "grad.hip", "kpm.hip", "dedup.hip", "api.cpp"]
+SOURCES = ["hamiltonian.hip", "made_bf16.hip", "made_f64.hip", "grad.hip", "kpm.hip", "dedup.hip", "sampler.hip", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions stay off in all device code

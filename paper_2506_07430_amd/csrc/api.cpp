@@ -905,6 +905,100 @@ elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz
   return ELOCAL_OK;
 }
 
+// ----------------------------------------------------------------------------- BAS sampler
+namespace {
+
+struct SampleWs {
+  void* frag;
+  void* bias;
+  uint64_t* pre[2];
+  int64_t* w[2];
+  double* probs;
+  int64_t* counts;
+  int64_t* off;
+  int64_t* btot;
+  int64_t* total;
+  size_t bytes;
+};
+
+SampleWs carve_sample(const elocal_ctx* h, const AnsatzGeom& G, int64_t cap, void* ws) {
+  Carve c(ws);
+  SampleWs w{};
+  const size_t C = (size_t)std::max<int64_t>(cap, 1), W = h->sys.W;
+  w.frag = c.take<char>(G.wbytes);
+  w.bias = c.take<char>(G.bbytes);
+  for (int k = 0; k < 2; ++k) {
+    w.pre[k] = c.take<uint64_t>(C * W);
+    w.w[k] = c.take<int64_t>(C);
+  }
+  w.probs = c.take<double>(4 * C);
+  w.counts = c.take<int64_t>(4 * C);
+  w.off = c.take<int64_t>(C);
+  w.btot = c.take<int64_t>((C + 1023) / 1024);
+  w.total = c.take<int64_t>(1);
+  w.bytes = c.off;
+  return w;
+}
+
+__global__ void k_sample_root(uint64_t* pre, int64_t* w, int W, int64_t n_samples) {
+  if (threadIdx.x < (unsigned)W) pre[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) w[0] = n_samples;
+}
+
+}  // namespace
+
+size_t elocal_sample_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t max_unique) {
+  if (!h) { fail(ELOCAL_E_INVALID, "handle is null"); return 0; }
+  AnsatzGeom G;
+  if (make_geom(h, a, G) != ELOCAL_OK) return 0;
+  return carve_sample(h, G, max_unique, nullptr).bytes;
+}
+
+elocal_status elocal_sample(elocal_t h, elocal_stream s, const elocal_ansatz* a, int64_t n_samples, uint64_t seed,
+                            int64_t max_unique, void* ws, size_t ws_bytes, uint64_t* x_out, int64_t* counts_out,
+                            int64_t* n_unique) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  AnsatzGeom G;
+  if (elocal_status e = make_geom(h, a, G)) return e;
+  if (G.precision != ELOCAL_FP64) return fail(ELOCAL_E_UNSUPPORTED, "the sampler evaluates the ansatz in FP64 only");
+  if (n_samples < 1 || n_samples > 0xFFFFFFFFll)
+    return fail(ELOCAL_E_INVALID, "n_samples=%lld outside [1, 2^32 - 1]", (long long)n_samples);
+  if (max_unique < 1) return fail(ELOCAL_E_INVALID, "max_unique < 1");
+  if (!a->theta || !ws || !x_out || !counts_out || !n_unique) return fail(ELOCAL_E_INVALID, "null pointer argument");
+  const SampleWs need = carve_sample(h, G, max_unique, nullptr);
+  if (ws_bytes < need.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
+  if (elocal_status st = check_device(h)) return st;
+  const SampleWs w = carve_sample(h, G, max_unique, ws);
+  hipStream_t st = (hipStream_t)s;
+  MadeDev M = G.md;
+  M.wfrag = w.frag;
+  M.bias = w.bias;
+  HIP_TRY(launch_pack_f64(M, G.T, (const double*)a->theta, w.frag, (double*)w.bias, st), "pack launch");
+  hipLaunchKernelGGL(k_sample_root, dim3(1), dim3(64), 0, st, w.pre[0], w.w[0], h->sys.W, n_samples);
+  HIP_TRY(hipGetLastError(), "root launch");
+  int64_t U = 1;
+  int cur = 0;
+  for (int k = 0; k < h->sys.n; ++k) {
+    HIP_TRY(launch_bas_step(h->sys, M, G.hmax, w.pre[cur], w.w[cur], U, k, seed, w.probs, w.counts, w.off, w.btot,
+                            w.total, w.pre[1 - cur], w.w[1 - cur], max_unique, st), "sampling step launch");
+    int64_t next = 0;
+    HIP_TRY(hipMemcpyAsync(&next, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, st), "count copy");
+    HIP_TRY(hipStreamSynchronize(st), "sampling step sync");
+    if (next > max_unique)
+      return fail(ELOCAL_E_WORKSPACE, "%lld distinct prefixes at orbital %d exceed max_unique=%lld", (long long)next,
+                  k, (long long)max_unique);
+    U = next;
+    cur = 1 - cur;
+  }
+  HIP_TRY(hipMemcpyAsync(x_out, w.pre[cur], (size_t)U * h->sys.W * sizeof(uint64_t), hipMemcpyDeviceToDevice, st),
+          "sample copy");
+  HIP_TRY(hipMemcpyAsync(counts_out, w.w[cur], (size_t)U * sizeof(int64_t), hipMemcpyDeviceToDevice, st),
+          "count copy");
+  HIP_TRY(hipStreamSynchronize(st), "sampling sync");
+  *n_unique = U;
+  return ELOCAL_OK;
+}
+
 // ----------------------------------------------------------------------------- deduplicated eval
 namespace {
 

@@ -312,6 +312,45 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Conditional of orbital k for every prefix: probs[i][s] (0 where s is not reachable).
+// FP64 network, 16 prefixes per wave (the layout of the FP64 sample pass).
+template <int HMAX, int NW>
+__global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, const uint64_t* __restrict__ pre,
+                                                   int64_t U, int k, double* __restrict__ probs) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t b0 = wave * 16;
+  if (b0 >= U) return;
+  const int n = S.n, na = S.na, nb = S.nb;
+  const int64_t rb = b0 + r16;
+  const int64_t bb = rb < U ? rb : b0;
+  uint64_t xr[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) xr[w] = pre[bb * NW + w];
+  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.bias, xr, lane, [&](int ob, const f64x4& z) {
+    if (4 * ob + g != k) return;
+    const int cu = count_spin_below<NW>(xr, k, 0), cd = count_spin_below<NW>(xr, k, 1);
+    const int left = n - k - 1;
+    bool ok[4];
+    double m = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int u = cu + (q & 1), d = cd + (q >> 1);
+      ok[q] = (u <= na) && (d <= nb) && (u + left >= na) && (d + left >= nb);
+      if (ok[q]) m = fmax(m, z[q]);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (ok[q]) sum += exp(z[q] - m);
+    const double lse = m + log(sum);
+    if (rb < U) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) probs[rb * 4 + q] = ok[q] ? exp(z[q] - lse) : 0.0;
+    }
+  });
+}
+
 hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta, void* frag,
                            double* bias, hipStream_t st) {
   const uint32_t total = M.nfrag * 64u > M.nbias ? M.nfrag * 64u : M.nbias;
@@ -372,6 +411,27 @@ hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream
     case 64: return eval_f64_h<64>(A, grid, st);
     case 128: return eval_f64_h<128>(A, grid, st);
     case 256: return eval_f64_h<256>(A, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int HMAX>
+static hipError_t bas_probs_h(const SysDev& S, const MadeDev& M, const uint64_t* pre, int64_t U, int k, double* probs,
+                              hipStream_t st) {
+  const int64_t waves = (U + 15) / 16;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  if (S.W == 1) hipLaunchKernelGGL((k_bas_probs<HMAX, 1>), dim3(blocks), dim3(256), 0, st, S, M, pre, U, k, probs);
+  else hipLaunchKernelGGL((k_bas_probs<HMAX, 2>), dim3(blocks), dim3(256), 0, st, S, M, pre, U, k, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bas_probs(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, int64_t U, int k,
+                            double* probs, hipStream_t st) {
+  switch (hmax) {
+    case 32: return bas_probs_h<32>(S, M, pre, U, k, probs, st);
+    case 64: return bas_probs_h<64>(S, M, pre, U, k, probs, st);
+    case 128: return bas_probs_h<128>(S, M, pre, U, k, probs, st);
+    case 256: return bas_probs_h<256>(S, M, pre, U, k, probs, st);
   }
   return hipErrorInvalidValue;
 }

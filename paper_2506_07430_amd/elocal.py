@@ -67,6 +67,9 @@ def lib():
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
         L.elocal_tune.argtypes = [vp, i32, i64]
+        L.elocal_sample_workspace_bytes.argtypes = [vp, P(_Ansatz), i64]
+        L.elocal_sample_workspace_bytes.restype = sz
+        L.elocal_sample.argtypes = [vp, vp, P(_Ansatz), i64, ctypes.c_uint64, i64, vp, sz, vp, vp, P(i64)]
         L.elocal_dedup_workspace_bytes.argtypes = [vp, P(_Ansatz), i64]
         L.elocal_dedup_workspace_bytes.restype = sz
         L.elocal_eval_dedup.argtypes = [vp, vp, P(_Ansatz), vp, i64, vp, sz, vp, vp, vp]
@@ -91,7 +94,7 @@ def lib():
         for f in ("elocal_create", "elocal_destroy", "elocal_connect", "elocal_eval", "elocal_stats",
                   "elocal_grad", "elocal_check_samples", "elocal_timing_enable", "elocal_kernel_timing", "elocal_tune",
                   "elocal_eval_multi", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
-                  "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_eval_pauli", "elocal_eval_dedup"):
+                  "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_eval_pauli", "elocal_eval_dedup", "elocal_sample"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -104,7 +107,8 @@ def exported_symbols() -> Sequence[str]:
             "elocal_workspace_bytes_multi", "elocal_eval_multi", "elocal_sector_dim",
             "elocal_sector_workspace_bytes", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
             "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_pauli_count", "elocal_pauli_workspace_bytes",
-            "elocal_eval_pauli", "elocal_dedup_workspace_bytes", "elocal_eval_dedup"]
+            "elocal_eval_pauli", "elocal_dedup_workspace_bytes", "elocal_eval_dedup", "elocal_sample_workspace_bytes",
+            "elocal_sample"]
 
 
 def _check(status: int):
@@ -268,6 +272,20 @@ class Hamiltonian:
         """Launch shape of the fused kernel (0 = built-in)."""
         _check(lib().elocal_tune(self._h, 0, int(grid)))
         _check(lib().elocal_tune(self._h, 1, int(groups)))
+
+    # ------------------------------------------------------------------ sampling
+    def sample(self, ansatz: Ansatz, n_samples: int, seed: int, max_unique: int = 1 << 20, stream=None):
+        """BAS draws from |Psi|^2: (distinct determinants [U, W] int64, counts [U] int64)."""
+        need = int(lib().elocal_sample_workspace_bytes(self._h, ansatz.ref(), int(max_unique)))
+        if need == 0:
+            raise ElocalError(1, lib().elocal_last_error().decode())
+        ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        x = torch.empty((int(max_unique), self.W), dtype=torch.int64, device=self.device)
+        c = torch.empty(int(max_unique), dtype=torch.int64, device=self.device)
+        u = ctypes.c_int64(0)
+        _check(lib().elocal_sample(self._h, _stream(stream), ansatz.ref(), int(n_samples), ctypes.c_uint64(seed),
+                                   int(max_unique), ws.data_ptr(), need, x.data_ptr(), c.data_ptr(), ctypes.byref(u)))
+        return x[:u.value], c[:u.value]
 
     # ------------------------------------------------------------------ deduplicated eval
     def eval_dedup(self, ansatz: Ansatz, x: torch.Tensor, out: Optional[torch.Tensor] = None,
