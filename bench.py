@@ -65,12 +65,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--cpu-samples", type=int, default=48)
+    ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the captured step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--sampler-draws", type=int, default=1_000_000,
+                    help="draws of the batch autoregressive sampler leg (FP64 ansatz of the workload); 0 skips")
     ap.add_argument("--pauli-samples", type=int, default=1024,
                     help="samples of the Pauli-string route leg (Algorithm 1 over unique flips); 0 skips")
     ap.add_argument("--kpm-moments", type=int, default=64,
@@ -225,6 +227,18 @@ def main():
                           "note": "prep + generator launches on the caller's stream, HIP events around them"}
         del outs
         torch.cuda.empty_cache()
+
+    # --- batch autoregressive sampling from the same ansatz (FP64 conditionals)
+    if args.sampler_draws > 0:
+        ham.sample(ans64, 1000, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs_, cs_ = ham.sample(ans64, args.sampler_draws, 2026)
+        t_s = time.perf_counter() - t0
+        out["sampler"] = {"draws": args.sampler_draws, "distinct": int(xs_.shape[0]), "seconds": t_s,
+                          "draws_per_s": args.sampler_draws / t_s, "orbital_steps": s.n,
+                          "note": "synchronous call (the tree size is read back per orbital)"}
+        del xs_, cs_
 
     # --- the paper's Pauli-string route on the same ansatz and samples: every unique flip
     # of the Jordan--Wigner strings goes through the ansatz (vs the C connected ones)
