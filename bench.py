@@ -38,19 +38,22 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 
 
 def unmasked_weights(n: int, widths) -> int:
-    """Weights the autoregressive mask keeps (degree rule of include/elocal.h), phase head included."""
+    """Weights the autoregressive mask keeps (degree rule of include/elocal.h) that E_loc needs,
+    phase head included. The last orbital's logits are left out: its conditional is 1 whatever
+    they are (one occupation keeps both electron counts reachable)."""
     deg_in = np.arange(2 * n) // 2 + 1
     hid = [np.arange(w) % (n - 1) + 1 for w in widths]
     total = int(np.sum(hid[0][:, None] >= deg_in[None, :]))
     for l in range(1, len(widths)):
         total += int(np.sum(hid[l][:, None] >= hid[l - 1][None, :]))
-    deg_out = np.arange(4 * n) // 4 + 1
+    deg_out = np.arange(4 * (n - 1)) // 4 + 1
     total += int(np.sum(deg_out[:, None] > hid[-1][None, :]))
     return total + widths[-1]
 
 
 def dense_weights(n: int, widths) -> int:
-    dims = [2 * n] + list(widths) + [4 * n]
+    """Weights of the same network without the mask (last orbital's logits left out)."""
+    dims = [2 * n] + list(widths) + [4 * (n - 1)]
     return sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1)) + widths[-1]
 
 

@@ -138,7 +138,9 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   uint32_t wo = 0, bo = 0;
   for (int l = 0; l <= L; ++l) {
     M.nin[l] = (l == 0) ? 2 * n : a->widths[l - 1];
-    M.nout[l] = (l == L) ? 4 * n + 1 : a->widths[l];
+    // output layer: 4 logits per orbital and the phase row; the BF16 packing drops the last
+    // orbital's logits (its conditional is 1) and puts the phase row in their place
+    M.nout[l] = (l < L) ? a->widths[l] : bf ? 4 * (n - 1) + 1 : 4 * n + 1;
     M.nk[l] = bf ? (M.nin[l] + 31) / 32 : (M.nin[l] + 3) / 4;
     M.nob[l] = (M.nout[l] + 15) / 16;
     M.woff[l] = wo;
@@ -166,7 +168,8 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
           const int mmax = deg_at(w, std::min(16 * ob + 15, w - 1));
           need = (l == 0) ? 2 * mmax : count_le(a->widths[l - 1], mmax);
         } else {
-          const bool phase = 16 * ob <= 4 * n && 4 * n < 16 * ob + 16;
+          const int ph = 4 * (n - 1);   // phase row of the BF16 packing
+          const bool phase = 16 * ob <= ph && ph < 16 * ob + 16;
           const int D = std::min(4 * ob + 3, n - 1);
           need = phase ? M.nin[l] : count_le(a->widths[L - 1], D);
         }

@@ -59,14 +59,15 @@ struct SampleCtx {
 };
 
 // Ansatz geometry after packing (shared by the BF16 and FP64 kernels).
-//   layer l in [0, L]: l < L hidden (ReLU), l == L output (4n logits + phase row 4n).
+//   layer l in [0, L]: l < L hidden (ReLU), l == L output: FP64 4n logits + phase row 4n;
+//         BF16 4(n - 1) logits + phase row 4(n - 1) (the last orbital's conditional is 1).
 //   BF16: input K split in k-blocks of 32, outputs in o-blocks of 16; one packed
 //         fragment (ob, kb) = 64 lanes x 8 bf16 = 1 KiB.
 //   FP64: input K split in k-steps of 4; fragment (ob, ks) = 64 lanes x 1 double.
 struct MadeDev {
   int n, L;
   int nin[kMaxLayers];     // input width of layer l (true, unpadded)
-  int nout[kMaxLayers];    // output width of layer l (true; output layer 4n + 1)
+  int nout[kMaxLayers];    // output width of layer l (true; output layer as above)
   int nk[kMaxLayers];      // k-blocks (BF16) or k-steps (FP64) of layer l
   int nob[kMaxLayers];     // 16-wide output blocks of layer l
   uint32_t woff[kMaxLayers];   // fragment offset of layer l in the packed buffer

@@ -26,11 +26,16 @@
 
 namespace elocal {
 
+// Output layer of the BF16 packing: rows 4p..4p+3 hold the logits of orbital p < n - 1 and
+// row 4(n - 1) the phase head. The last orbital needs no logits: with no orbital left after
+// it exactly one occupation keeps both electron counts reachable, so its conditional is 1.
+__device__ __forceinline__ int phase_row_bf16(int n) { return 4 * (n - 1); }
+
 __device__ __forceinline__ bool made_allowed(int n, int L, int l, int o, int k) {
   const int nm1 = n - 1;
   if (l == 0) return (o % nm1) + 1 >= k / 2 + 1;
   if (l < L) return (o % nm1) + 1 >= (k % nm1) + 1;
-  if (o == 4 * n) return true;              // phase head sees the whole last layer
+  if (o == phase_row_bf16(n)) return true;   // phase head sees the whole last layer
   return (o / 4) + 1 > (k % nm1) + 1;
 }
 
@@ -65,7 +70,7 @@ __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict
       if (kpos < M.nin[l]) k = (l == 0) ? kpos : sorted_unit(n, M.nin[l], kpos);
       unsigned short bits = 0;
       if (o >= 0 && k >= 0 && made_allowed(n, L, l, o, k)) {
-        if (l == L && o == 4 * n) bits = theta[T.offwphi + k];
+        if (l == L && o == phase_row_bf16(n)) bits = theta[T.offwphi + k];
         else bits = theta[T.offW[l] + (uint32_t)o * M.nin[l] + k];
       }
       v[j] = bits;
@@ -81,7 +86,7 @@ __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict
     unsigned short bits = 0;
     if (orow < M.nout[l]) {
       if (l < L) bits = theta[T.offb[l] + sorted_unit(n, M.nout[l], orow)];
-      else bits = (orow == 4 * n) ? theta[T.offbphi] : theta[T.offb[l] + orow];
+      else bits = (orow == phase_row_bf16(n)) ? theta[T.offbphi] : theta[T.offb[l] + orow];
     }
     bias[gid] = __uint_as_float((uint32_t)bits << 16);
   }
@@ -393,13 +398,13 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
 #pragma unroll
     for (int w = 0; w < NW; ++w) xr[c][w] = P.x[bb * NW + w];
   }
-  const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
+  const int ob_phi = phase_row_bf16(n) >> 4, g_phi = (phase_row_bf16(n) & 15) >> 2;
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
   RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], min(g, n - 1)), cursor_at<NW>(xr[1], min(g, n - 1))};
   mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, 0, [&](int ob, const f32x4& a0, const f32x4& a1) {
     const int p = 4 * ob + g;
-    if (p < n) {
+    if (p < n - 1) {   // the last orbital's conditional is 1
       const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -497,7 +502,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
   const SysDev& S = P.sys;
   const int g = lane >> 4, r16 = lane & 15;
   const int n = S.n, na = S.na, nb = S.nb;
-  const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
+  const int ob_phi = phase_row_bf16(n) >> 4, g_phi = (phase_row_bf16(n) & 15) >> 2;
   const int64_t b = item / P.ips;
   const uint32_t seg = (uint32_t)(item % P.ips);
   if (b != st.b) {
@@ -507,7 +512,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
     build_ctx<NW>(S, st.xs, wc.c, lane);
     {
       // suffix sums of the sample's log2 p in FP64 (a fixed shuffle tree)
-      double v = lane < n ? (double)P.lpx[b * n + lane] : 0.0;
+      double v = lane < n - 1 ? (double)P.lpx[b * n + lane] : 0.0;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const double u = __shfl_down(v, off);
@@ -560,7 +565,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], pfirst), cursor_at<NW>(xr[1], pfirst)};
       mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
         const int p = 4 * ob + g;
-        if (p < n) {
+        if (p < n - 1) {   // the last orbital's conditional is 1
           const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
