@@ -174,6 +174,8 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
           need = phase ? M.nin[l] : count_le(a->widths[L - 1], D);
         }
         M.kend[l][ob] = std::min(M.nk[l], (need + 31) / 32);
+        // the kernels issue k-block 0 of every block unconditionally
+        if (M.kend[l][ob] < 1) return fail(ELOCAL_E_UNSUPPORTED, "empty k-range in layer %d", l);
       }
     }
   }
@@ -208,7 +210,7 @@ struct EvalPlan {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 // per-wave LDS contexts of the BF16 kernel (every wave of a block)
-constexpr size_t kCtxBytesBF16 = kMaxEvalWavesBF16 * kWaveCtxBytesBF16;
+constexpr size_t kCtxBytesBF16 = kBlockLdsBF16;   // wave contexts + input table
 
 // Persistent grid: 32 waves per CU in total (a few rounds of resident blocks), unless tuned.
 int64_t grid_cap(const elocal_ctx* h, int waves) {

@@ -76,6 +76,11 @@ constexpr int kMaxEvalWavesBF16 = 8;
 // Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists and
 // the FP64 suffix sums of its per-orbital log2 probabilities.
 constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(double);
+// Input-expansion table of the fused BF16 kernels, in LDS after the wave contexts: entry v
+// holds the 8 bf16 values (bit j of v ? 1 : 0), the layer-0 operand of 8 input bits.
+constexpr size_t kXLutBytes = 256 * 16;
+// LDS a fused BF16 block needs beyond the staged weights and biases.
+constexpr size_t kBlockLdsBF16 = kMaxEvalWavesBF16 * kWaveCtxBytesBF16 + kXLutBytes;
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system
 // s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax, nterms) work items each (LDS layout as
 // for one system: weights at 0, biases at bias_off, wave contexts at ctx_off). FP64:

@@ -119,6 +119,9 @@ __device__ __forceinline__ void split_pair(float u, float v, uint32_t (&t)[NT]) 
     h[1] = (__bf16)v;
     uint32_t hb;
     __builtin_memcpy(&hb, &h, 4);
+    // opaque to the optimiser: without this it recomputes bf16(u) by a second convert
+    // instead of taking it from hb
+    asm volatile("" : "+v"(hb));
     t[i] = hb;
     if (i + 1 < NT) {
       u -= __uint_as_float(hb << 16);
@@ -155,6 +158,9 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
   return r;
 }
 
+// Every block sees at least its first k-block (kend >= 1, checked when the ansatz is
+// packed), so k-block 0 is issued unconditionally in the layers below.
+
 // Output block ob of the last layer for both column blocks (rows r and 16 + r).
 template <int KB, int NT>
 __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ W,
@@ -165,7 +171,7 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __rest
   const bf16x8* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
-    if (kb < ke) {
+    if (kb == 0 || kb < ke) {
       const bf16x8 w = wp[kb * 64];
 #pragma unroll
       for (int c = 0; c < 2; ++c)
@@ -179,11 +185,13 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __rest
 // epi(ob, acc_c0, acc_c1) for the output blocks ob >= ob_first (earlier blocks belong
 // to orbitals the caller does not need). Hidden activations are carried as NT bf16
 // terms (one MFMA per term and weight fragment).
-template <int HMAX, int NW, int NT, class Epi>
+// With XLUT the layer-0 operands come from the LDS table xlut (kXLutBytes), else they are
+// expanded from the bits in registers.
+template <int HMAX, int NW, int NT, bool XLUT = false, class Epi>
 __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restrict__ W,
                                          const float* __restrict__ bias,
                                          const uint64_t (&xr)[2][NW], int lane, int ob_first,
-                                         Epi&& epi) {
+                                         const bf16x8* xlut, Epi&& epi) {
   constexpr int KB = HMAX / 32;
   const int g = lane >> 4;
   bf16x8 act[NT][2][KB];
@@ -195,7 +203,8 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
-        xin[c][kb] = bits_to_bf16x8(kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
+        if (XLUT) xin[c][kb] = xlut[kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u];
+        else xin[c][kb] = bits_to_bf16x8(kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
@@ -207,11 +216,11 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
         const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          if (kb < ke1) {
+          if (kb == 0 || kb < ke1) {
             const bf16x8 w1 = w1p[kb * 64];
             a1[0] = mfma_bf16(w1, xin[0][kb], a1[0]);
             a1[1] = mfma_bf16(w1, xin[1][kb], a1[1]);
-            if (kb < ke0) {
+            if (kb == 0 || kb < ke0) {
               const bf16x8 w0 = w0p[kb * 64];
               a0[0] = mfma_bf16(w0, xin[0][kb], a0[0]);
               a0[1] = mfma_bf16(w0, xin[1][kb], a0[1]);
@@ -243,13 +252,13 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
         const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-          if (kb < ke1) {
+          if (kb == 0 || kb < ke1) {
             const bf16x8 w1 = w1p[kb * 64];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
               for (int i = 0; i < NT; ++i) a1[c] = mfma_bf16(w1, act[i][c][kb], a1[c]);
-            if (kb < ke0) {
+            if (kb == 0 || kb < ke0) {
               const bf16x8 w0 = w0p[kb * 64];
 #pragma unroll
               for (int c = 0; c < 2; ++c)
@@ -402,7 +411,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
   RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], min(g, n - 1)), cursor_at<NW>(xr[1], min(g, n - 1))};
-  mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, 0, [&](int ob, const f32x4& a0, const f32x4& a1) {
+  mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4& a0, const f32x4& a1) {
     const int p = 4 * ob + g;
     if (p < n - 1) {   // the last orbital's conditional is 1
       const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
@@ -496,8 +505,8 @@ struct PauliGen {
 
 template <int HMAX, int NW, int NT, class Gen = ScGen>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* __restrict__ W,
-                                               const float* __restrict__ bias, WaveCtxBF16& wc,
-                                               int64_t item, SampleState<NW>& st, int lane) {
+                                               const float* __restrict__ bias, const bf16x8* xlut,
+                                               WaveCtxBF16& wc, int64_t item, SampleState<NW>& st, int lane) {
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
   const int g = lane >> 4, r16 = lane & 15;
@@ -563,14 +572,15 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       float zp[2] = {0.f, 0.f};
       const int pfirst = min(4 * ob_first + g, n - 1);
       RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], pfirst), cursor_at<NW>(xr[1], pfirst)};
-      mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, ob_first, [&](int ob, const f32x4& a0, const f32x4& a1) {
+      mlp_bf16<HMAX, NW, NT, true>(M, W, bias, xr, lane, ob_first, xlut, [&](int ob, const f32x4& a0, const f32x4& a1) {
         const int p = 4 * ob + g;
         if (p < n - 1) {   // the last orbital's conditional is 1
           const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
-            const float d = p >= p0[c] ? lp : 0.f;
+            float d = p >= p0[c] ? lp : 0.f;
+            asm volatile("" : "+v"(d));   // keeps the select in 32 bits (before the convert)
             dA[c] += (double)d;     // sum over p >= p0 of log2 p(x'); x's part is subtracted below
           }
         }
@@ -624,6 +634,15 @@ __device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* s
   for (uint32_t i = threadIdx.x; i < M.nbias; i += blockDim.x) sb[i] = gb[i];
 }
 
+// Fills the input-expansion table (every thread of the block takes part; the caller
+// synchronises the block before the table is read).
+__device__ __forceinline__ bf16x8* fill_xlut(unsigned char* smem, uint32_t ctx_off) {
+  static_assert((kMaxEvalWavesBF16 * kWaveCtxBytesBF16) % 16 == 0, "input table alignment");
+  bf16x8* lut = (bf16x8*)(smem + ctx_off + kMaxEvalWavesBF16 * kWaveCtxBytesBF16);
+  for (uint32_t v = threadIdx.x; v < 256u; v += blockDim.x) lut[v] = bits_to_bf16x8(v);
+  return lut;
+}
+
 // One system; a persistent grid strides over the work items, one wave per item. With
 // LDSW the packed weights and biases are first staged in LDS.
 template <int HMAX, int NW, int NT, bool LDSW>
@@ -633,18 +652,19 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   const bf16x8* W = (const bf16x8*)P.made.wfrag;
   const float* bias = (const float*)P.made.bias;
+  const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
     stage_weights(P.made, smem, P.lds_bias_off);
-    __syncthreads();
     W = (const bf16x8*)smem;
     bias = (const float*)(smem + P.lds_bias_off);
   }
+  __syncthreads();
   WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + P.lds_ctx_off))[wid];
   SampleState<NW> st;
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, NW, NT>(P, W, bias, wc, item, st, lane);
+    eval_item_bf16<HMAX, NW, NT>(P, W, bias, xlut, wc, item, st, lane);
 }
 
 // Pauli-string route: the fused kernel over the unique flip masks of every sample (one
@@ -656,18 +676,19 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   const bf16x8* W = (const bf16x8*)P.made.wfrag;
   const float* bias = (const float*)P.made.bias;
+  const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
     stage_weights(P.made, smem, P.lds_bias_off);
-    __syncthreads();
     W = (const bf16x8*)smem;
     bias = (const float*)(smem + P.lds_bias_off);
   }
+  __syncthreads();
   WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + P.lds_ctx_off))[wid];
   SampleState<1> st;
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, 1, NT, PauliGen>(P, W, bias, wc, item, st, lane);
+    eval_item_bf16<HMAX, 1, NT, PauliGen>(P, W, bias, xlut, wc, item, st, lane);
 }
 
 // Several systems in one persistent launch. Work is cut into chunks of kEvalWaves items
@@ -689,6 +710,8 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
   int cur = -1;
   const bf16x8* W = nullptr;
   const float* bias = nullptr;
+  const bf16x8* xlut = fill_xlut(smem, lds_ctx_off);
+  __syncthreads();
   const int64_t chunks = first[n_sys];
   for (int64_t chunk = blockIdx.x; chunk < chunks; chunk += gridDim.x) {
     int s = 0;
@@ -711,8 +734,8 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
     }
     const int64_t local = (chunk - first[s]) * kEvalWaves + wid;
     if (local < P.n_items) {
-      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT>(P, W, bias, wc, local, st1, lane);
-      else eval_item_bf16<HMAX, 2, NT>(P, W, bias, wc, local, st2, lane);
+      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT>(P, W, bias, xlut, wc, local, st1, lane);
+      else eval_item_bf16<HMAX, 2, NT>(P, W, bias, xlut, wc, local, st2, lane);
     }
   }
 }
