@@ -126,6 +126,30 @@ def test_eval_bf16_c0():
     assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("precision", [elocal.BF16, elocal.BF16X3])
+@pytest.mark.parametrize("n,na,nb,widths", [(2, 1, 1, (32,)), (3, 1, 2, (32,)), (5, 2, 1, (32,)),
+                                             (5, 0, 3, (64,)), (12, 6, 5, (64, 32)), (33, 8, 9, (32, 32)),
+                                             (17, 8, 8, (256,)), (64, 3, 2, (64,))])
+def test_eval_bf16_shapes(n, na, nb, widths, precision):
+    """Shapes at the packing's edges: a single orbital with logits (n = 2), the phase row
+    alone in an output block (n = 5), an empty spin block, the word boundary (n = 33),
+    the width-256 kernels and the largest n; local energies and log psi of samples drawn
+    from the ansatz (uniformly drawn determinants of the sparse 64-orbital sector have
+    ratios psi(x')/psi(x) up to e^21, whose FP32 log-softmax rounding alone exceeds the bar)."""
+    p = synth.random_problem(n, na, nb, widths, seed=300 + n + na, n_chol=4, decay=5.0, samples=1)
+    _, th_or = theta_for(p.theta, precision)
+    x = ansatz_samples(p, min(5, math.comb(n, na) * math.comb(n, nb)), seed=n, theta=th_or)
+    el, lp, th = _eval(p, x, precision)
+    ref = _oracle_eloc(p, x, th)
+    A, phi = oen.log_psi(th, x, n, na, nb, widths)
+    err = np.abs(el - ref)
+    print(f"n={n} ({na},{nb}) {widths}: max |dE_loc| = {err.max():.3e}, "
+          f"max |dA| = {np.max(np.abs(lp[:, 0] - A)):.2e}, max |dphi| = {np.max(np.abs(lp[:, 1] - phi)):.2e}")
+    assert err.max() <= 1e-5
+    assert np.max(np.abs(lp[:, 0] - A)) <= 1e-4
+    assert np.max(np.abs(lp[:, 1] - phi)) <= 1e-4
+
+
 @pytest.mark.parametrize("precision", [elocal.BF16X3])
 def test_eval_bf16x3_c0_and_n24(precision):
     """Three bf16 terms per activation: within 1e-5 Ha, and closer than two terms."""
