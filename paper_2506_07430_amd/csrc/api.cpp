@@ -150,10 +150,12 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   }
   M.nfrag = wo;
   M.nbias = bo;
-  // k-block ranges of the degree-sorted BF16 packing (FP64 packing is unsorted: full range)
-  for (int l = 0; l <= L; ++l)
-    for (int ob = 0; ob < kMaxOutBlocks; ++ob) M.kend[l][ob] = M.nk[l];
-  if (bf) {
+  // k-ranges of the degree-sorted packing: o-block ob of layer l needs the inputs of
+  // degree <= the block's largest degree, a prefix of the (sorted) input order. BF16:
+  // k-blocks of 32 inputs. FP64: k-steps of 4; layer 0 takes inputs 4ks..4ks+3, later
+  // layers take one unit of each 4-unit group of a 16-unit block, so a prefix of units
+  // is covered by whole 16-unit blocks (4 k-steps each).
+  {
     auto deg_at = [&](int width, int u) { return sorted_unit(n, width, u) % (n - 1) + 1; };
     auto count_le = [&](int width, int D) {
       int c = 0;
@@ -161,6 +163,7 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
       return c;
     };
     for (int l = 0; l <= L; ++l) {
+      for (int ob = 0; ob < kMaxOutBlocks; ++ob) M.kend[l][ob] = M.nk[l];
       for (int ob = 0; ob < M.nob[l]; ++ob) {
         int need;   // input units (or bits) this block can see
         if (l < L) {
@@ -168,13 +171,16 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
           const int mmax = deg_at(w, std::min(16 * ob + 15, w - 1));
           need = (l == 0) ? 2 * mmax : count_le(a->widths[l - 1], mmax);
         } else {
-          const int ph = 4 * (n - 1);   // phase row of the BF16 packing
+          const int ph = bf ? 4 * (n - 1) : 4 * n;   // phase row
           const bool phase = 16 * ob <= ph && ph < 16 * ob + 16;
           const int D = std::min(4 * ob + 3, n - 1);
           need = phase ? M.nin[l] : count_le(a->widths[L - 1], D);
         }
-        M.kend[l][ob] = std::min(M.nk[l], (need + 31) / 32);
-        // the kernels issue k-block 0 of every block unconditionally
+        int ke;
+        if (bf) ke = (need + 31) / 32;
+        else ke = (l == 0) ? (need + 3) / 4 : 4 * ((need + 15) / 16);
+        M.kend[l][ob] = std::min(M.nk[l], ke);
+        // the BF16 kernels issue k-block 0 of every block unconditionally
         if (M.kend[l][ob] < 1) return fail(ELOCAL_E_UNSUPPORTED, "empty k-range in layer %d", l);
       }
     }

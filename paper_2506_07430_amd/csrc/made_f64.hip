@@ -6,7 +6,9 @@
 // register i, so the packer stores weight row 16*ob + 4*(rho%4) + rho/4 at A-row rho;
 // lane group g then holds units 16*ob + 4g + i in register i, exactly as in the BF16
 // path, and register i of block ob is the B operand of k-step 4*ob + i of the next
-// layer. Output orbital 4*ob + g again lands in one lane.
+// layer. Output orbital 4*ob + g again lands in one lane. Hidden units are stored in
+// degree order, so o-block ob of layer l only needs its first kend[l][ob] k-steps (whole
+// 16-unit blocks of the previous layer; the rest of its weights are masked).
 #include "elocal_internal.hpp"
 #include "kernels.hpp"
 
@@ -31,8 +33,11 @@ __global__ void k_pack_f64(MadeDev M, ThetaLayout T, const double* __restrict__ 
     const uint32_t local = f - M.woff[l];
     const int ob = local / M.nk[l], ks = local % M.nk[l];
     const int rho = lane & 15, g = lane >> 4;
-    const int o = 16 * ob + 4 * (rho & 3) + (rho >> 2);
-    const int k = (l == 0) ? 4 * ks + g : 16 * (ks >> 2) + 4 * g + (ks & 3);
+    const int opos = 16 * ob + 4 * (rho & 3) + (rho >> 2);
+    const int kpos = (l == 0) ? 4 * ks + g : 16 * (ks >> 2) + 4 * g + (ks & 3);
+    // hidden units in degree order (as in the BF16 packing); inputs and logits unsorted
+    const int o = (l < M.L && opos < M.nout[l]) ? sorted_unit(M.n, M.nout[l], opos) : opos;
+    const int k = (l > 0 && kpos < M.nin[l]) ? sorted_unit(M.n, M.nin[l], kpos) : kpos;
     double v = 0.0;
     if (o < M.nout[l] && k < M.nin[l] && made_allowed64(M.n, M.L, l, o, k)) {
       if (l == M.L && o == 4 * M.n) v = theta[T.offwphi + k];
@@ -43,9 +48,12 @@ __global__ void k_pack_f64(MadeDev M, ThetaLayout T, const double* __restrict__ 
   if (gid < M.nbias) {
     int l = 0;
     while (l < M.L && gid >= M.boff[l + 1]) ++l;
-    const int o = gid - M.boff[l];
+    const int opos = gid - M.boff[l];
     double v = 0.0;
-    if (o < M.nout[l]) v = (l == M.L && o == 4 * M.n) ? theta[T.offbphi] : theta[T.offb[l] + o];
+    if (opos < M.nout[l]) {
+      const int o = (l < M.L) ? sorted_unit(M.n, M.nout[l], opos) : opos;
+      v = (l == M.L && o == 4 * M.n) ? theta[T.offbphi] : theta[T.offb[l] + o];
+    }
     bias[gid] = v;
   }
 }
@@ -81,9 +89,10 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       if (ob < nob) {
+        const int ke = __builtin_amdgcn_readfirstlane(M.kend[0][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[0] + 16 * ob + 4 * g);
         const double* wp = W + (size_t)(M.woff[0] + ob * nk) * 64 + lane;
-        for (int ks = 0; ks < nk; ++ks) {
+        for (int ks = 0; ks < ke; ++ks) {
           const double bv = (double)getbit<NW>(xr, 4 * ks + g);
           acc = mfma_f64(wp[ks * 64], bv, acc);
         }
@@ -97,11 +106,12 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       if (ob < nob) {
+        const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
         const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
-          if (ks < nk) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
+          if (ks < ke) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
         nxt[ob] = relu4(acc);
       }
     }
@@ -112,11 +122,12 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
     const int l = M.L, nk = M.nk[l], nob = M.nob[l];
 #pragma unroll 1
     for (int ob = 0; ob < nob; ++ob) {
+      const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
       f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
       const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
-        if (ks < nk) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
+        if (ks < ke) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
       epi(ob, acc);
     }
   }
