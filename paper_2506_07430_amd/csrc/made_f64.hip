@@ -75,6 +75,35 @@ __device__ __forceinline__ f64x4 relu4(const f64x4& a) {
   return r;
 }
 
+// k-steps [0, ke) of one o-block: f(ks, w) with w = wp[64 ks], the weight loads running
+// two chunks of four k-steps ahead of the products that use them (one wave per SIMD has
+// nothing else to hide the load latency with).
+template <int KSMAX, class F>
+__device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke, F&& f) {
+  constexpr int CH = 4, LA = 2, NC = (KSMAX + CH - 1) / CH;
+  double w[NC][CH];
+#pragma unroll
+  for (int c = 0; c < LA && c < NC; ++c)
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if (c * CH + j < ke) w[c][j] = wp[(c * CH + j) * 64];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    // keeps the scheduler from hoisting later chunks' loads (their registers) above this point
+    __builtin_amdgcn_sched_barrier(0);
+    if (c * CH < ke) {
+      if (c + LA < NC) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+          if ((c + LA) * CH + j < ke) w[c + LA][j] = wp[((c + LA) * CH + j) * 64];
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (c * CH + j < ke) f(c * CH + j, w[c][j]);
+    }
+  }
+}
+
 // Network on one 16-row block (row r of lane r); epi(ob, acc) per output block.
 template <int HMAX, int NW, class Epi>
 __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ W,
@@ -82,6 +111,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
                                         int lane, Epi&& epi) {
   constexpr int OB = HMAX / 16;
   constexpr int KS = HMAX / 4;
+  constexpr int KS0 = 2 * kMaxOrb / 4;   // k-steps of the input layer (2n <= 128 bits)
   const int g = lane >> 4;
   f64x4 cur[OB];
   {
@@ -109,9 +139,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
         const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-          if (ks < ke) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
+        kloop_f64<KS>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
         nxt[ob] = relu4(acc);
       }
     }
@@ -125,9 +153,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
       const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
       f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
       const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        if (ks < ke) acc = mfma_f64(wp[ks * 64], cur[ks >> 2][ks & 3], acc);
+      kloop_f64<KS>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
       epi(ob, acc);
     }
   }
