@@ -76,11 +76,12 @@ __device__ __forceinline__ f64x4 relu4(const f64x4& a) {
 }
 
 // k-steps [0, ke) of one o-block: f(ks, w) with w = wp[64 ks], the weight loads running
-// two chunks of four k-steps ahead of the products that use them (one wave per SIMD has
-// nothing else to hide the load latency with).
-template <int KSMAX, class F>
+// two chunks of CH k-steps ahead of the products that use them (one wave per SIMD has
+// nothing else to hide the load latency with). CH = 8 measured best at width <= 128;
+// width 256 keeps CH = 4 (fewer registers).
+template <int KSMAX, int CH, class F>
 __device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke, F&& f) {
-  constexpr int CH = 4, LA = 2, NC = (KSMAX + CH - 1) / CH;
+  constexpr int LA = 2, NC = (KSMAX + CH - 1) / CH;
   double w[NC][CH];
 #pragma unroll
   for (int c = 0; c < LA && c < NC; ++c)
@@ -111,7 +112,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
                                         int lane, Epi&& epi) {
   constexpr int OB = HMAX / 16;
   constexpr int KS = HMAX / 4;
-  constexpr int KS0 = 2 * kMaxOrb / 4;   // k-steps of the input layer (2n <= 128 bits)
+  constexpr int KCH = HMAX >= 256 ? 4 : 8;   // k-steps per weight-load chunk
   const int g = lane >> 4;
   f64x4 cur[OB];
   {
@@ -139,7 +140,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
         const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
-        kloop_f64<KS>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+        kloop_f64<KS, KCH>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
         nxt[ob] = relu4(acc);
       }
     }
@@ -153,7 +154,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
       const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
       f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
       const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
-      kloop_f64<KS>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+      kloop_f64<KS, KCH>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
       epi(ob, acc);
     }
   }
