@@ -209,6 +209,7 @@ struct EvalPlan {
   uint32_t rows_per_tile, tpi, ips;
   int64_t n_items;
   bool ldsw;
+  size_t lds_w;   // BF16: staged weight bytes (aligned); biases follow, then the wave contexts
   size_t lds;
   int waves;        // waves per block
   unsigned grid;
@@ -224,6 +225,14 @@ int64_t grid_cap(const elocal_ctx* h, int waves) {
   return (int64_t)h->cu_count * (32 / waves);
 }
 
+// Bytes of packed BF16 weights a fused block of a width-`kernel_hmax` kernel stages in
+// LDS: all of them, or from kLdsPartialWidth on layer 0 and the output layer only.
+static size_t staged_wbytes(const AnsatzGeom& G, int kernel_hmax) {
+  if (kernel_hmax < kLdsPartialWidth) return G.wbytes;
+  const MadeDev& M = G.md;
+  return (size_t)(M.woff[1] + (M.nfrag - M.woff[M.L])) * 64 * 16;
+}
+
 EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t list_len = -1) {
   EvalPlan p{};
   // BF16: groups of 64 entries (one per lane), 8 per item; FP64: tiles of 16, 16 per item
@@ -236,7 +245,8 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
   p.n_items = (int64_t)p.ips * B;
   if (G.precision == ELOCAL_BF16) {
-    const size_t need = align256(G.wbytes) + align256(G.bbytes) + kCtxBytesBF16;
+    p.lds_w = align256(staged_wbytes(G, G.hmax));
+    const size_t need = p.lds_w + align256(G.bbytes) + kCtxBytesBF16;
     p.ldsw = need <= kLdsBytes;   // one 8-wave block per CU owns the CU's LDS
     p.lds = p.ldsw ? need : kCtxBytesBF16;
     p.waves = eval_waves_bf16(G.hmax, G.nterms);
@@ -555,8 +565,8 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
   if (timed) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
   if (G.precision == ELOCAL_BF16) {
     if (p.ldsw) {
-      E.lds_bias_off = (uint32_t)align256(G.wbytes);
-      E.lds_ctx_off = (uint32_t)(align256(G.wbytes) + align256(G.bbytes));
+      E.lds_bias_off = (uint32_t)p.lds_w;
+      E.lds_ctx_off = (uint32_t)(p.lds_w + align256(G.bbytes));
     } else {
       E.lds_bias_off = 0;
       E.lds_ctx_off = 0;
@@ -632,7 +642,7 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
   size_t wmax = 0, bmax = 0;
   for (int s = 0; s < n_sys; ++s) {
-    wmax = std::max(wmax, align256(M.G[s].wbytes));
+    wmax = std::max(wmax, align256(staged_wbytes(M.G[s], M.hmax)));
     bmax = std::max(bmax, align256(M.G[s].bbytes));
   }
   if (M.precision == ELOCAL_BF16) {
@@ -899,8 +909,8 @@ elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz
   EvalArgs E{};
   E.sys = h->sys; E.made = M; E.x = x; E.B = B; E.ediag = w.ediag; E.F = w.F; E.lpx = w.lpx; E.zphi = w.zphi;
   E.partial = w.partial; E.n_items = p.n_items; E.ips = p.ips; E.tpi = p.tpi;
-  E.lds_bias_off = p.ldsw ? (uint32_t)align256(G.wbytes) : 0;
-  E.lds_ctx_off = p.ldsw ? (uint32_t)(align256(G.wbytes) + align256(G.bbytes)) : 0;
+  E.lds_bias_off = p.ldsw ? (uint32_t)p.lds_w : 0;
+  E.lds_ctx_off = p.ldsw ? (uint32_t)(p.lds_w + align256(G.bbytes)) : 0;
   E.pl_mask = h->d_pl_mask; E.pl_off = h->d_pl_off; E.pl_z = h->d_pl_z; E.pl_coef = h->d_pl_coef;
   E.pl_len = (uint32_t)h->pl_len;
   const bool timed = h->timing && p.n_items > 0;

@@ -79,6 +79,9 @@ constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(
 // Input-expansion table of the fused BF16 kernels, in LDS after the wave contexts: entry v
 // holds the 8 bf16 values (bit j of v ? 1 : 0), the layer-0 operand of 8 input bits.
 constexpr size_t kXLutBytes = 256 * 16;
+// Fused BF16 kernels of at least this width stage only layer 0 and the output layer in
+// LDS (their hidden layers do not fit) and read the hidden layers from global memory.
+constexpr int kLdsPartialWidth = 256;
 // LDS a fused BF16 block needs beyond the staged weights and biases.
 constexpr size_t kBlockLdsBF16 = kMaxEvalWavesBF16 * kWaveCtxBytesBF16 + kXLutBytes;
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system

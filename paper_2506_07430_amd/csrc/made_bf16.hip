@@ -161,14 +161,41 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
 // Every block sees at least its first k-block (kend >= 1, checked when the ansatz is
 // packed), so k-block 0 is issued unconditionally in the layers below.
 
+// Where the packed weights are read from: layer 0 and the output layer each from its own
+// base (fragment 0 of the layer), the hidden layers from a base indexed by woff[l]. All
+// three point into LDS when the whole network is staged; with partial staging (width 256,
+// whose hidden layers do not fit) layer 0 and the output layer are in LDS and the hidden
+// layers in global memory.
+struct WeightsBF16 {
+  const bf16x8* hid;
+  const bf16x8* l0;
+  const bf16x8* out;
+};
+
+// Partial staging (layer 0 and the output layer only) for the widest networks.
+template <int HMAX>
+constexpr bool lds_partial_bf16() { return HMAX >= kLdsPartialWidth; }
+
+__device__ __forceinline__ WeightsBF16 weights_global(const MadeDev& M) {
+  const bf16x8* W = (const bf16x8*)M.wfrag;
+  return {W, W, W + (size_t)M.woff[M.L] * 64};
+}
+
+template <int HMAX>
+__device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsigned char* smem) {
+  const bf16x8* S = (const bf16x8*)smem;
+  if (lds_partial_bf16<HMAX>()) return {(const bf16x8*)M.wfrag, S, S + (size_t)M.woff[1] * 64};
+  return {S, S, S + (size_t)M.woff[M.L] * 64};
+}
+
 // Output block ob of the last layer for both column blocks (rows r and 16 + r).
 template <int KB, int NT>
-__device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ W,
+__device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ WL,
                                           const float* __restrict__ bias, const bf16x8 (&act)[NT][2][KB],
                                           int ob, int lane, f32x4 (&a)[2]) {
   const int l = M.L, nk = M.nk[l], ke = sgpr(M.kend[l][ob]);
   a[0] = a[1] = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
-  const bf16x8* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
+  const bf16x8* wp = WL + (size_t)(ob * nk) * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     if (kb == 0 || kb < ke) {
@@ -188,7 +215,7 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __rest
 // With XLUT the layer-0 operands come from the LDS table xlut (kXLutBytes), else they are
 // expanded from the bits in registers.
 template <int HMAX, int NW, int NT, bool XLUT = false, class Epi>
-__device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restrict__ W,
+__device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt,
                                          const float* __restrict__ bias,
                                          const uint64_t (&xr)[2][NW], int lane, int ob_first,
                                          const bf16x8* xlut, Epi&& epi) {
@@ -212,7 +239,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
         f32x4 a0[2], a1[2];
         a0[0] = a0[1] = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
         a1[0] = a1[1] = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
-        const bf16x8* w0p = W + (size_t)(M.woff[0] + (2 * kbo) * nk) * 64 + lane;
+        const bf16x8* w0p = Wt.l0 + (size_t)((2 * kbo) * nk) * 64 + lane;
         const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
@@ -248,7 +275,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
         f32x4 a0[2], a1[2];
         a0[0] = a0[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
         a1[0] = a1[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
-        const bf16x8* w0p = W + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
+        const bf16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
         const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
@@ -289,7 +316,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const bf16x8* __restr
 #pragma unroll 1
     for (int ob = sgpr(ob_first); ob < nob; ++ob) {
       f32x4 acc[2];
-      out_block<KB, NT>(M, W, bias, act, ob, lane, acc);
+      out_block<KB, NT>(M, Wt.out, bias, act, ob, lane, acc);
       epi(ob, acc[0], acc[1]);
     }
   }
@@ -396,7 +423,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   if (b0 >= Bn) return;
   const MadeDev& M = P.made;
   const int n = P.sys.n, na = P.sys.na, nb = P.sys.nb;
-  const bf16x8* W = (const bf16x8*)M.wfrag;
+  const WeightsBF16 Wt = weights_global(M);
   const float* bias = (const float*)M.bias;
   uint64_t xr[2][NW];
   int64_t rb[2];
@@ -411,7 +438,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
   RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], min(g, n - 1)), cursor_at<NW>(xr[1], min(g, n - 1))};
-  mlp_bf16<HMAX, NW, NT>(M, W, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4& a0, const f32x4& a1) {
+  mlp_bf16<HMAX, NW, NT>(M, Wt, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4& a0, const f32x4& a1) {
     const int p = 4 * ob + g;
     if (p < n - 1) {   // the last orbital's conditional is 1
       const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
@@ -504,7 +531,7 @@ struct PauliGen {
 };
 
 template <int HMAX, int NW, int NT, class Gen = ScGen>
-__device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* __restrict__ W,
+__device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsBF16& Wt,
                                                const float* __restrict__ bias, const bf16x8* xlut,
                                                WaveCtxBF16& wc, int64_t item, SampleState<NW>& st, int lane) {
   const MadeDev& M = P.made;
@@ -572,7 +599,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
       float zp[2] = {0.f, 0.f};
       const int pfirst = min(4 * ob_first + g, n - 1);
       RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], pfirst), cursor_at<NW>(xr[1], pfirst)};
-      mlp_bf16<HMAX, NW, NT, true>(M, W, bias, xr, lane, ob_first, xlut, [&](int ob, const f32x4& a0, const f32x4& a1) {
+      mlp_bf16<HMAX, NW, NT, true>(M, Wt, bias, xr, lane, ob_first, xlut, [&](int ob, const f32x4& a0, const f32x4& a1) {
         const int p = 4 * ob + g;
         if (p < n - 1) {   // the last orbital's conditional is 1
           const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
@@ -625,10 +652,20 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const bf16x8* 
 // Block shape of the fused kernels: one block per CU, so the whole 160 KiB of LDS can
 // hold the packed weights of one ansatz; 8 waves (two per SIMD) up to width 128.
 
+// Copies the packed weights (all of them, or with PARTIAL layer 0 followed by the output
+// layer) and the biases into LDS.
+template <bool PARTIAL>
 __device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* smem, uint32_t bias_off) {
   bf16x8* sw = (bf16x8*)smem;
   const bf16x8* gw = (const bf16x8*)M.wfrag;
-  for (uint32_t i = threadIdx.x; i < M.nfrag * 64u; i += blockDim.x) sw[i] = gw[i];
+  if (PARTIAL) {
+    const uint32_t n0 = M.woff[1] * 64u, nl = (M.nfrag - M.woff[M.L]) * 64u;
+    const bf16x8* gl = gw + (size_t)M.woff[M.L] * 64;
+    for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) sw[i] = gw[i];
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) sw[n0 + i] = gl[i];
+  } else {
+    for (uint32_t i = threadIdx.x; i < M.nfrag * 64u; i += blockDim.x) sw[i] = gw[i];
+  }
   float* sb = (float*)(smem + bias_off);
   const float* gb = (const float*)M.bias;
   for (uint32_t i = threadIdx.x; i < M.nbias; i += blockDim.x) sb[i] = gb[i];
@@ -644,18 +681,19 @@ __device__ __forceinline__ bf16x8* fill_xlut(unsigned char* smem, uint32_t ctx_o
 }
 
 // One system; a persistent grid strides over the work items, one wave per item. With
-// LDSW the packed weights and biases are first staged in LDS.
+// LDSW the packed weights (at width 256 those of layer 0 and the output layer) and the
+// biases are first staged in LDS.
 template <int HMAX, int NW, int NT, bool LDSW>
 __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16(EvalArgs P) {
   constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
-  const bf16x8* W = (const bf16x8*)P.made.wfrag;
+  WeightsBF16 Wt = weights_global(P.made);
   const float* bias = (const float*)P.made.bias;
   const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
-    stage_weights(P.made, smem, P.lds_bias_off);
-    W = (const bf16x8*)smem;
+    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off);
+    Wt = weights_lds<HMAX>(P.made, smem);
     bias = (const float*)(smem + P.lds_bias_off);
   }
   __syncthreads();
@@ -664,7 +702,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, NW, NT>(P, W, bias, xlut, wc, item, st, lane);
+    eval_item_bf16<HMAX, NW, NT>(P, Wt, bias, xlut, wc, item, st, lane);
 }
 
 // Pauli-string route: the fused kernel over the unique flip masks of every sample (one
@@ -674,12 +712,12 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
-  const bf16x8* W = (const bf16x8*)P.made.wfrag;
+  WeightsBF16 Wt = weights_global(P.made);
   const float* bias = (const float*)P.made.bias;
   const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
-    stage_weights(P.made, smem, P.lds_bias_off);
-    W = (const bf16x8*)smem;
+    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off);
+    Wt = weights_lds<HMAX>(P.made, smem);
     bias = (const float*)(smem + P.lds_bias_off);
   }
   __syncthreads();
@@ -688,7 +726,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, 1, NT, PauliGen>(P, W, bias, xlut, wc, item, st, lane);
+    eval_item_bf16<HMAX, 1, NT, PauliGen>(P, Wt, bias, xlut, wc, item, st, lane);
 }
 
 // Several systems in one persistent launch. Work is cut into chunks of kEvalWaves items
@@ -708,7 +746,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
   SampleState<2> st2;
   st1.b = st2.b = -1;
   int cur = -1;
-  const bf16x8* W = nullptr;
+  WeightsBF16 Wt = {nullptr, nullptr, nullptr};
   const float* bias = nullptr;
   const bf16x8* xlut = fill_xlut(smem, lds_ctx_off);
   __syncthreads();
@@ -723,19 +761,19 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
       st1.b = st2.b = -1;
       if (LDSW) {
         __syncthreads();   // every wave is done with the previous system's weights
-        stage_weights(P.made, smem, lds_bias_off);
+        stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, lds_bias_off);
         __syncthreads();
-        W = (const bf16x8*)smem;
+        Wt = weights_lds<HMAX>(P.made, smem);
         bias = (const float*)(smem + lds_bias_off);
       } else {
-        W = (const bf16x8*)P.made.wfrag;
+        Wt = weights_global(P.made);
         bias = (const float*)P.made.bias;
       }
     }
     const int64_t local = (chunk - first[s]) * kEvalWaves + wid;
     if (local < P.n_items) {
-      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT>(P, W, bias, xlut, wc, local, st1, lane);
-      else eval_item_bf16<HMAX, 2, NT>(P, W, bias, xlut, wc, local, st2, lane);
+      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT>(P, Wt, bias, xlut, wc, local, st1, lane);
+      else eval_item_bf16<HMAX, 2, NT>(P, Wt, bias, xlut, wc, local, st2, lane);
     }
   }
 }
