@@ -210,6 +210,7 @@ struct EvalPlan {
   int64_t n_items;
   bool ldsw;
   size_t lds_w;   // BF16: staged weight bytes (aligned); biases follow, then the wave contexts
+  uint32_t lds_l0;   // BF16 partial staging: layer 0 staged too
   size_t lds;
   int waves;        // waves per block
   unsigned grid;
@@ -225,12 +226,19 @@ int64_t grid_cap(const elocal_ctx* h, int waves) {
   return (int64_t)h->cu_count * (32 / waves);
 }
 
-// Bytes of packed BF16 weights a fused block of a width-`kernel_hmax` kernel stages in
-// LDS: all of them, or from kLdsPartialWidth on layer 0 and the output layer only.
-static size_t staged_wbytes(const AnsatzGeom& G, int kernel_hmax) {
-  if (kernel_hmax < kLdsPartialWidth) return G.wbytes;
+// Bytes of packed BF16 weights (aligned) a fused block of a width-`kernel_hmax` kernel
+// stages in LDS: all of them, or from kLdsPartialWidth on the output layer, followed by
+// layer 0 if both fit beside the biases and the wave contexts (*l0 = 1).
+static size_t staged_wbytes(const AnsatzGeom& G, int kernel_hmax, uint32_t* l0) {
+  *l0 = 0;
+  if (kernel_hmax < kLdsPartialWidth) return align256(G.wbytes);
   const MadeDev& M = G.md;
-  return (size_t)(M.woff[1] + (M.nfrag - M.woff[M.L])) * 64 * 16;
+  const size_t out = (size_t)(M.nfrag - M.woff[M.L]) * 64 * 16, first = (size_t)M.woff[1] * 64 * 16;
+  if (align256(out + first) + align256(G.bbytes) + kCtxBytesBF16 <= kLdsBytes) {
+    *l0 = 1;
+    return align256(out + first);
+  }
+  return align256(out);
 }
 
 EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t list_len = -1) {
@@ -245,7 +253,7 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
   p.n_items = (int64_t)p.ips * B;
   if (G.precision == ELOCAL_BF16) {
-    p.lds_w = align256(staged_wbytes(G, G.hmax));
+    p.lds_w = staged_wbytes(G, G.hmax, &p.lds_l0);
     const size_t need = p.lds_w + align256(G.bbytes) + kCtxBytesBF16;
     p.ldsw = need <= kLdsBytes;   // one 8-wave block per CU owns the CU's LDS
     p.lds = p.ldsw ? need : kCtxBytesBF16;
@@ -567,6 +575,7 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
     if (p.ldsw) {
       E.lds_bias_off = (uint32_t)p.lds_w;
       E.lds_ctx_off = (uint32_t)(p.lds_w + align256(G.bbytes));
+      E.lds_l0 = p.lds_l0;
     } else {
       E.lds_bias_off = 0;
       E.lds_ctx_off = 0;
@@ -597,6 +606,7 @@ struct MultiPlan {
   int64_t first[ELOCAL_MAX_SYSTEMS + 1];
   int hmax, precision;
   bool ldsw;            // BF16: every system's weights fit in LDS
+  uint32_t l0[ELOCAL_MAX_SYSTEMS];   // BF16 partial staging: system s stages layer 0 too
   uint32_t bias_off, ctx_off;
   size_t lds;
   unsigned grid;
@@ -642,7 +652,9 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
   size_t wmax = 0, bmax = 0;
   for (int s = 0; s < n_sys; ++s) {
-    wmax = std::max(wmax, align256(staged_wbytes(M.G[s], M.hmax)));
+    uint32_t l0;
+    wmax = std::max(wmax, staged_wbytes(M.G[s], M.hmax, &l0));
+    M.l0[s] = l0;
     bmax = std::max(bmax, align256(M.G[s].bbytes));
   }
   if (M.precision == ELOCAL_BF16) {
@@ -719,7 +731,7 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
     E.sys = h->sys; E.made = M.G[i].md; E.made.wfrag = W[i].frag; E.made.bias = W[i].bias;
     E.x = x[i]; E.B = B[i]; E.ediag = W[i].ediag; E.F = W[i].F; E.lpx = W[i].lpx; E.lpx64 = W[i].lpx64;
     E.zphi = W[i].zphi; E.partial = W[i].partial; E.n_items = M.p[i].n_items; E.ips = M.p[i].ips;
-    E.tpi = M.p[i].tpi; E.lds_bias_off = 0; E.lds_ctx_off = 0;
+    E.tpi = M.p[i].tpi; E.lds_bias_off = 0; E.lds_ctx_off = 0; E.lds_l0 = M.l0[i];
     HIP_TRY(launch_store_bytes(&E, sizeof(EvalArgs), (char*)d_args + kArgsStride * k, st), "argument store");
   }
   HIP_TRY(launch_store_bytes(M.first, sizeof(int64_t) * (n_sys + 1), d_first, st), "argument store");
@@ -911,6 +923,7 @@ elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz
   E.partial = w.partial; E.n_items = p.n_items; E.ips = p.ips; E.tpi = p.tpi;
   E.lds_bias_off = p.ldsw ? (uint32_t)p.lds_w : 0;
   E.lds_ctx_off = p.ldsw ? (uint32_t)(p.lds_w + align256(G.bbytes)) : 0;
+  E.lds_l0 = p.lds_l0;
   E.pl_mask = h->d_pl_mask; E.pl_off = h->d_pl_off; E.pl_z = h->d_pl_z; E.pl_coef = h->d_pl_coef;
   E.pl_len = (uint32_t)h->pl_len;
   const bool timed = h->timing && p.n_items > 0;

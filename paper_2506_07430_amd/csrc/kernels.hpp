@@ -28,6 +28,8 @@ struct EvalArgs {
   uint32_t tpi;            // row tiles per work item
   uint32_t lds_bias_off;   // byte offset of the biases in LDS (weights at 0)
   uint32_t lds_ctx_off;    // byte offset of the per-wave contexts
+  uint32_t lds_l0;         // partial staging (width >= kLdsPartialWidth): layer 0 staged after
+                           // the output layer (1) or read from global memory (0)
   // Pauli-string route only: unique flip masks [pl_len], string offsets [pl_len + 1],
   // string Z masks and real coefficients [pl_off[pl_len]]
   const uint64_t* pl_mask;
@@ -79,8 +81,9 @@ constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(
 // Input-expansion table of the fused BF16 kernels, in LDS after the wave contexts: entry v
 // holds the 8 bf16 values (bit j of v ? 1 : 0), the layer-0 operand of 8 input bits.
 constexpr size_t kXLutBytes = 256 * 16;
-// Fused BF16 kernels of at least this width stage only layer 0 and the output layer in
-// LDS (their hidden layers do not fit) and read the hidden layers from global memory.
+// Fused BF16 kernels of at least this width stage only the output layer, followed by
+// layer 0 when it fits too, in LDS (their hidden layers do not fit) and read the rest
+// from global memory.
 constexpr int kLdsPartialWidth = 256;
 // LDS a fused BF16 block needs beyond the staged weights and biases.
 constexpr size_t kBlockLdsBF16 = kMaxEvalWavesBF16 * kWaveCtxBytesBF16 + kXLutBytes;

@@ -164,8 +164,8 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
 // Where the packed weights are read from: layer 0 and the output layer each from its own
 // base (fragment 0 of the layer), the hidden layers from a base indexed by woff[l]. All
 // three point into LDS when the whole network is staged; with partial staging (width 256,
-// whose hidden layers do not fit) layer 0 and the output layer are in LDS and the hidden
-// layers in global memory.
+// whose hidden layers do not fit) the output layer is in LDS, followed by layer 0 when it
+// fits too (then read through a generic pointer), and the hidden layers in global memory.
 struct WeightsBF16 {
   const bf16x8* hid;
   const bf16x8* l0;
@@ -182,9 +182,12 @@ __device__ __forceinline__ WeightsBF16 weights_global(const MadeDev& M) {
 }
 
 template <int HMAX>
-__device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsigned char* smem) {
+__device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsigned char* smem, uint32_t l0) {
   const bf16x8* S = (const bf16x8*)smem;
-  if (lds_partial_bf16<HMAX>()) return {(const bf16x8*)M.wfrag, S, S + (size_t)M.woff[1] * 64};
+  if (lds_partial_bf16<HMAX>()) {
+    const bf16x8* G = (const bf16x8*)M.wfrag;
+    return {G, l0 ? S + (size_t)(M.nfrag - M.woff[M.L]) * 64 : G, S};
+  }
   return {S, S, S + (size_t)M.woff[M.L] * 64};
 }
 
@@ -652,17 +655,18 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
 // Block shape of the fused kernels: one block per CU, so the whole 160 KiB of LDS can
 // hold the packed weights of one ansatz; 8 waves (two per SIMD) up to width 128.
 
-// Copies the packed weights (all of them, or with PARTIAL layer 0 followed by the output
-// layer) and the biases into LDS.
+// Copies the packed weights (all of them, or with PARTIAL the output layer followed, if
+// l0, by layer 0) and the biases into LDS.
 template <bool PARTIAL>
-__device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* smem, uint32_t bias_off) {
+__device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* smem, uint32_t bias_off,
+                                              uint32_t l0) {
   bf16x8* sw = (bf16x8*)smem;
   const bf16x8* gw = (const bf16x8*)M.wfrag;
   if (PARTIAL) {
-    const uint32_t n0 = M.woff[1] * 64u, nl = (M.nfrag - M.woff[M.L]) * 64u;
+    const uint32_t n0 = l0 ? M.woff[1] * 64u : 0u, nl = (M.nfrag - M.woff[M.L]) * 64u;
     const bf16x8* gl = gw + (size_t)M.woff[M.L] * 64;
-    for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) sw[i] = gw[i];
-    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) sw[n0 + i] = gl[i];
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) sw[i] = gl[i];
+    for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) sw[nl + i] = gw[i];
   } else {
     for (uint32_t i = threadIdx.x; i < M.nfrag * 64u; i += blockDim.x) sw[i] = gw[i];
   }
@@ -681,8 +685,8 @@ __device__ __forceinline__ bf16x8* fill_xlut(unsigned char* smem, uint32_t ctx_o
 }
 
 // One system; a persistent grid strides over the work items, one wave per item. With
-// LDSW the packed weights (at width 256 those of layer 0 and the output layer) and the
-// biases are first staged in LDS.
+// LDSW the packed weights (at width 256 the output layer and, if it fits, layer 0) and
+// the biases are first staged in LDS.
 template <int HMAX, int NW, int NT, bool LDSW>
 __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16(EvalArgs P) {
   constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
@@ -692,8 +696,8 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   const float* bias = (const float*)P.made.bias;
   const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
-    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off);
-    Wt = weights_lds<HMAX>(P.made, smem);
+    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off, P.lds_l0);
+    Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
     bias = (const float*)(smem + P.lds_bias_off);
   }
   __syncthreads();
@@ -716,8 +720,8 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   const float* bias = (const float*)P.made.bias;
   const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
-    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off);
-    Wt = weights_lds<HMAX>(P.made, smem);
+    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off, P.lds_l0);
+    Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
     bias = (const float*)(smem + P.lds_bias_off);
   }
   __syncthreads();
@@ -761,9 +765,9 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
       st1.b = st2.b = -1;
       if (LDSW) {
         __syncthreads();   // every wave is done with the previous system's weights
-        stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, lds_bias_off);
+        stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, lds_bias_off, P.lds_l0);
         __syncthreads();
-        Wt = weights_lds<HMAX>(P.made, smem);
+        Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
         bias = (const float*)(smem + lds_bias_off);
       } else {
         Wt = weights_global(P.made);
