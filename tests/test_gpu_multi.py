@@ -6,7 +6,8 @@ scheduling of work items over the grid differs. Values are also checked against 
 FP64 oracle (BF16 mode within 1e-5 Ha on the same BF16-rounded parameters; FP64 mode
 within 1e-8 relative). The systems are those of the eight-system workload (n = 12..40
 at half filling, two hidden layers of 128; n = 36 and 40 need two words per
-determinant), with reduced sample counts, an empty batch and a single sample.
+determinant), with reduced sample counts, an empty batch and a single sample; and a
+launch that mixes width-256 networks with narrower ones.
 """
 import numpy as np
 import pytest
@@ -14,7 +15,7 @@ import torch
 
 from oracle import energy as oen
 from paper_2506_07430_amd import elocal, synth
-from tests.gpu_common import make_ham, theta_for, words_to_dev
+from tests.gpu_common import ansatz_samples, make_ham, theta_for, words_to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -70,6 +71,37 @@ def test_multi_equals_single_and_oracle(precision, counts, oracle_systems):
             assert np.max(np.abs(got - ref)) <= 1e-5
         else:
             assert np.all(np.abs(got - ref) <= 1e-8 * np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", [elocal.BF16, elocal.BF16X3])
+def test_multi_mixed_widths_one_launch(precision):
+    """A width-256 system (its kernels stage only part of the network in LDS) beside
+    narrower ones: the launch runs at width 256 for all of them, and every system must
+    still get exactly its single-system result."""
+    shapes = [(12, 6, 6, (256, 256)), (16, 8, 8, (128,)), (10, 5, 4, (64, 32)), (33, 4, 5, (256,))]
+    probs, hams, ans, xs = [], [], [], []
+    for i, (n, na, nb, widths) in enumerate(shapes):
+        p = synth.random_problem(n, na, nb, widths, seed=500 + i, n_chol=4, decay=5.0, samples=1)
+        th_dev, th_or = theta_for(p.theta, precision)
+        x = ansatz_samples(p, 6 + 3 * i, seed=i, theta=th_or)
+        probs.append((p, x, th_or))
+        hams.append(make_ham(p))
+        ans.append(elocal.Ansatz(widths, th_dev, precision))
+        xs.append(words_to_dev(x))
+    multi, lps = elocal.MultiEval()(hams, ans, xs, want_logpsi=True)
+    torch.cuda.synchronize()
+    for si, (h, a, x) in enumerate(zip(hams, ans, xs)):
+        single, lp1 = h.eval(a, x)
+        torch.cuda.synchronize()
+        assert torch.equal(multi[si], single), f"system {si}: multi-system result differs from single"
+        assert torch.equal(lps[si], lp1)
+    for si in (0, 3):
+        p, x, th = probs[si]
+        s = p.system
+        ref = oen.local_energies(p.h1e, p.eri, s.n, s.n_alpha, s.n_beta, s.widths, th, x[:2])
+        err = np.max(np.abs(_c(multi[si])[:2] - ref))
+        print(f"system {si} (n={s.n}, widths {s.widths}): max |dE_loc| = {err:.2e}", flush=True)
+        assert err <= 1e-5
 
 
 def test_multi_rejects_mixed_precision_and_bad_counts():
