@@ -123,9 +123,17 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[0][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[0] + 16 * ob + 4 * g);
         const double* wp = W + (size_t)(M.woff[0] + ob * nk) * 64 + lane;
-        for (int ks = 0; ks < ke; ++ks) {
-          const double bv = (double)getbit<NW>(xr, 4 * ks + g);
-          acc = mfma_f64(wp[ks * 64], bv, acc);
+        if constexpr (NW == 1 && HMAX <= 128) {
+          // one-word determinants (2n <= 64 bits, at most 16 k-steps): loads run ahead
+          kloop_f64<16, 4>(wp, ke, [&](int ks, double w) {
+            acc = mfma_f64(w, (double)getbit<NW>(xr, 4 * ks + g), acc);
+          });
+        } else {
+          // longer inputs or wider networks: the registers for prefetching are not there
+          for (int ks = 0; ks < ke; ++ks) {
+            const double bv = (double)getbit<NW>(xr, 4 * ks + g);
+            acc = mfma_f64(wp[ks * 64], bv, acc);
+          }
         }
         cur[ob] = relu4(acc);
       }
