@@ -106,10 +106,12 @@ __device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke,
 }
 
 // Network on one 16-row block (row r of lane r); epi(ob, acc) per output block.
+// W: packed weights (layer l at fragment woff[l]); WL: the output layer's fragment 0,
+// which may be a copy in LDS.
 template <int HMAX, int NW, class Epi>
 __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ W,
-                                        const double* __restrict__ bias, const uint64_t (&xr)[NW],
-                                        int lane, Epi&& epi) {
+                                        const double* __restrict__ WL, const double* __restrict__ bias,
+                                        const uint64_t (&xr)[NW], int lane, Epi&& epi) {
   constexpr int OB = HMAX / 16;
   constexpr int KS = HMAX / 4;
   constexpr int KCH = HMAX >= 256 ? 4 : 8;   // k-steps per weight-load chunk
@@ -161,7 +163,7 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
     for (int ob = 0; ob < nob; ++ob) {
       const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
       f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
-      const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
+      const double* wp = WL + (size_t)(ob * nk) * 64 + lane;
       kloop_f64<KS, KCH>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
       epi(ob, acc);
     }
@@ -212,7 +214,8 @@ __global__ void __launch_bounds__(256) k_rows_f64(RowsArgs P) {
   for (int w = 0; w < NW; ++w) xr[w] = P.x[bb * NW + w];
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
   double A = 0.0, zp = 0.0;
-  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.bias, xr, lane,
+  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.wfrag + (size_t)M.woff[M.L] * 64,
+                    (const double*)M.bias, xr, lane,
                     [&](int ob, const f64x4& a) {
                       const int p = 4 * ob + g;
                       if (p < n) {
@@ -250,8 +253,8 @@ struct SampleState64 {
 // One work item = one sample and P.tpi tiles of 16 list entries; the 64 lanes of a tile
 // share its 16 rows (lane group g holds output units 4g..4g+3 of each 16-unit block).
 template <int HMAX, int NW>
-__device__ __forceinline__ void eval_item_f64(const EvalArgs& P, WaveCtx64& wc, int64_t item,
-                                              SampleState64<NW>& st, int lane) {
+__device__ __forceinline__ void eval_item_f64(const EvalArgs& P, const double* __restrict__ WL, WaveCtx64& wc,
+                                              int64_t item, SampleState64<NW>& st, int lane) {
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
   const double* W = (const double*)M.wfrag;
@@ -294,7 +297,7 @@ __device__ __forceinline__ void eval_item_f64(const EvalArgs& P, WaveCtx64& wc, 
     }
     const int p0 = first_diff_orbital<NW>(xs, xp, n);
     double dA = 0.0, zp = 0.0;
-    mlp_f64<HMAX, NW>(M, W, bias, xp, lane, [&](int ob, const f64x4& a) {
+    mlp_f64<HMAX, NW>(M, W, WL, bias, xp, lane, [&](int ob, const f64x4& a) {
       const int p = 4 * ob + g;
       if (p < n && p >= p0) dA += cond_logp64<NW>(xp, p, n, na, nb, a) - wc.lpx[p];
       if (ob == ob_phi && g == g_phi) zp = a[0];
@@ -322,14 +325,25 @@ __device__ __forceinline__ void eval_item_f64(const EvalArgs& P, WaveCtx64& wc, 
   }
 }
 
-template <int HMAX, int NW>
+// With LDSO the output layer's packed weights are first copied to LDS (dynamic shared
+// memory of nob[L] * nk[L] fragments).
+template <int HMAX, int NW, bool LDSO>
 __global__ void __launch_bounds__(256) k_eval_f64(EvalArgs P) {
   __shared__ WaveCtx64 ctxs[4];
+  extern __shared__ __attribute__((aligned(16))) double wout[];
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MadeDev& M = P.made;
+  const double* WL = (const double*)M.wfrag + (size_t)M.woff[M.L] * 64;
+  if (LDSO) {
+    const uint32_t cnt = (uint32_t)(M.nob[M.L] * M.nk[M.L]) * 64u;
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) wout[i] = WL[i];
+    __syncthreads();
+    WL = wout;
+  }
   SampleState64<NW> st;
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < P.n_items; item += (int64_t)gridDim.x * 4)
-    eval_item_f64<HMAX, NW>(P, ctxs[wid], item, st, lane);
+    eval_item_f64<HMAX, NW>(P, WL, ctxs[wid], item, st, lane);
 }
 
 // Several systems in one persistent launch (item index space as in the BF16 kernel).
@@ -353,8 +367,10 @@ __global__ void __launch_bounds__(256)
     }
     const EvalArgs& P = args[s];
     const int64_t local = item - first[s];
-    if (P.sys.W == 1) eval_item_f64<HMAX, 1>(P, ctxs[wid], local, st1, lane);
-    else eval_item_f64<HMAX, 2>(P, ctxs[wid], local, st2, lane);
+    if (P.sys.W == 1) eval_item_f64<HMAX, 1>(P, (const double*)P.made.wfrag + (size_t)P.made.woff[P.made.L] * 64, ctxs[wid],
+                                                 local, st1, lane);
+    else eval_item_f64<HMAX, 2>(P, (const double*)P.made.wfrag + (size_t)P.made.woff[P.made.L] * 64, ctxs[wid],
+                                            local, st2, lane);
   }
 }
 
@@ -373,7 +389,8 @@ __global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, const ui
   uint64_t xr[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) xr[w] = pre[bb * NW + w];
-  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.bias, xr, lane, [&](int ob, const f64x4& z) {
+  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.wfrag + (size_t)M.woff[M.L] * 64,
+                    (const double*)M.bias, xr, lane, [&](int ob, const f64x4& z) {
     if (4 * ob + g != k) return;
     const int cu = count_spin_below<NW>(xr, k, 0), cd = count_spin_below<NW>(xr, k, 1);
     const int left = n - k - 1;
@@ -425,11 +442,35 @@ hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+// Launches k_eval_f64 with the output layer in LDS when it fits beside the kernel's
+// static LDS (one 4-wave block per CU), else reading it from global memory.
+template <int HMAX, int NW>
+static hipError_t eval_f64_nw(const EvalArgs& A, unsigned grid, hipStream_t st) {
+  constexpr size_t kLds = 160 * 1024;
+  static size_t static_lds = ~(size_t)0;   // the same on every device of this build
+  if (static_lds == ~(size_t)0) {
+    hipFuncAttributes fa;
+    const hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_eval_f64<HMAX, NW, true>);
+    if (e != hipSuccess) return e;
+    static_lds = fa.sharedSizeBytes;
+  }
+  const size_t out = (size_t)A.made.nob[A.made.L] * A.made.nk[A.made.L] * 64 * sizeof(double);
+  if (static_lds + out <= kLds) {
+    if (out > 65536) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_eval_f64<HMAX, NW, true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)out);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_eval_f64<HMAX, NW, true>), dim3(grid), dim3(256), out, st, A);
+  } else {
+    hipLaunchKernelGGL((k_eval_f64<HMAX, NW, false>), dim3(grid), dim3(256), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
 template <int HMAX>
 static hipError_t eval_f64_h(const EvalArgs& A, unsigned grid, hipStream_t st) {
-  if (A.sys.W == 1) hipLaunchKernelGGL((k_eval_f64<HMAX, 1>), dim3(grid), dim3(256), 0, st, A);
-  else hipLaunchKernelGGL((k_eval_f64<HMAX, 2>), dim3(grid), dim3(256), 0, st, A);
-  return hipGetLastError();
+  return A.sys.W == 1 ? eval_f64_nw<HMAX, 1>(A, grid, st) : eval_f64_nw<HMAX, 2>(A, grid, st);
 }
 
 template <int HMAX>
