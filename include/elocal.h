@@ -70,9 +70,9 @@ enum {
   ELOCAL_FP64 = 0,   /* theta is double; ansatz on FP64 matrix cores                     */
   ELOCAL_BF16 = 1,   /* theta is bfloat16 (uint16 bit patterns); ansatz GEMMs on BF16
                         matrix cores with FP32 accumulation, each hidden activation
-                        carried as a hi+lo pair of bfloat16 values (~2^-18 relative)      */
+                        carried as a hi+lo pair of bfloat16 values (<= 2^-16 relative)    */
   ELOCAL_BF16X3 = 2  /* as ELOCAL_BF16 with three bfloat16 terms per activation
-                        (~2^-27 relative; 1.5x the matrix-core work after the first
+                        (<= 2^-24 relative; 1.5x the matrix-core work after the first
                         layer). The rounding of the two-term split, summed over a very
                         long connected list, grows past 1e-5 Ha per local energy around
                         n = 60 (1.1e6 connected determinants); three terms keep it below */

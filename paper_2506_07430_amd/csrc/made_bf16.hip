@@ -16,9 +16,11 @@
 // o-block ob of layer l multiplies only its first kend[l][ob] k-blocks.
 //
 // Precision: layer-0 inputs are exact 0/1; every later activation a (FP32 after bias
-// and ReLU) is fed as hi = bf16(a) plus lo = bf16(a - hi), two MFMAs per weight
-// fragment, so the representation error is ~2^-16 |a|. Accumulation is FP32; the
-// ratio exp(dA + i dphi), the matrix element and every sum are FP64.
+// and ReLU) is fed as hi = bf16(a) plus lo = bf16(a - hi) (a third term in the
+// three-term mode), one MFMA per term and weight fragment. bf16 keeps 8 significant
+// bits, so two terms represent a to within 2^-16 |a| and three to within 2^-24 |a|.
+// Accumulation is FP32; the ratio exp(dA + i dphi), the matrix element and every sum
+// are FP64.
 #include <type_traits>
 
 #include "elocal_internal.hpp"
@@ -107,7 +109,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // ReLU of a pair, then NT bfloat16 terms whose sum represents each value: t[0] =
 // bf16(a), t[1] = bf16(a - t[0]), t[2] = bf16(a - t[0] - t[1]) (one packed convert per
 // term for both values; the FP32 value of a term is recovered from its bits). Two terms
-// leave ~2^-18 |a|, three ~2^-27 |a|.
+// leave at most 2^-16 |a|, three 2^-24 |a|.
 template <int NT>
 __device__ __forceinline__ void split_pair(float u, float v, uint32_t (&t)[NT]) {
   u = __int_as_float(max(__float_as_int(u), 0));     // ReLU: negative floats are negative ints
