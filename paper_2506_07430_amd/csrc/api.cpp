@@ -605,7 +605,7 @@ struct MultiPlan {
   size_t args_off, first_off, bytes;
   int64_t first[ELOCAL_MAX_SYSTEMS + 1];
   int hmax, precision;
-  bool ldsw;            // BF16: every system's weights fit in LDS
+  bool ldsw;            // BF16: every system's staged weights fit in LDS
   uint32_t l0[ELOCAL_MAX_SYSTEMS];   // BF16 partial staging: system s stages layer 0 too
   uint32_t bias_off, ctx_off;
   size_t lds;
