@@ -52,10 +52,22 @@ __device__ __forceinline__ uint32_t spin_rank(const uint32_t* __restrict__ binom
   return r;
 }
 
+// One single excitation of a row: the change of its spin's rank and (I, A, parity of
+// the single applied alone).
+struct KpmSingle {
+  int32_t drank;
+  uint32_t info;   // I | A << 8 | parity << 16
+};
+
 // y = ch (H v) + cv v + cz z over the whole sector (z may be null); per wave, the
 // partial sums of y.y and y.v over its rows (fixed row order) go to partial[wave].
-// LDS per wave (stride `wstride` bytes): the row's SampleCtx, then its nSa + nSb
-// single-excitation values.
+// LDS per wave (stride `wstride` bytes): the row's SampleCtx, its nSa + nSb
+// single-excitation values, then its table of single excitations. Singles and
+// opposite-spin doubles (an alpha single u1 with a beta single u2) come from the table:
+// x' has rank (ra + drank(u1)) C(n, n_beta) + rb + drank(u2), and applying a_I, a_J, a+_B,
+// a+_A in that order has parity par(u1) + par(u2) + [I < J] + [I < B] + [J < A] + [B < A]
+// (each later operator also counts the orbitals the earlier ones emptied or filled below
+// it). The same-spin doubles go through the generator and rank only their spin.
 template <int NW>
 __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* __restrict__ binom, int64_t dim,
                                                       uint32_t nb_dim, double ch, double cv,
@@ -64,10 +76,15 @@ __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* 
                                                       double* __restrict__ partial, uint32_t wstride) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t nS = S.nSa + S.nSb;
   struct {
     SampleCtx& c;
     double* F;
-  } wc{*(SampleCtx*)(smem + wid * wstride), (double*)(smem + wid * wstride + sizeof(SampleCtx))};
+    KpmSingle* T;
+  } wc{*(SampleCtx*)(smem + wid * wstride), (double*)(smem + wid * wstride + sizeof(SampleCtx)),
+       (KpmSingle*)(smem + wid * wstride + sizeof(SampleCtx) + 8u * nS)};
+  const uint32_t ab0 = 1u + nS + S.nDaa + S.nDbb;   // first opposite-spin double
+  const int n = S.n;
   const int64_t wave = (int64_t)blockIdx.x * 4 + wid, nwaves = (int64_t)gridDim.x * 4;
   double yy = 0.0, yv = 0.0;
   for (int64_t r = wave; r < dim; r += nwaves) {
@@ -82,6 +99,21 @@ __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double ed = sample_terms<NW>(S, x, wc.c, lane, wc.F);
+    for (uint32_t u = lane; u < nS; u += 64) {
+      const int spin = u >= S.nSa;
+      const uint32_t w = spin ? u - S.nSa : u;
+      const uint32_t q = spin ? fdiv(w, S.f_vb) : fdiv(w, S.f_va);
+      const int I = 2 * wc.c.occ[spin][q] + spin, A = 2 * wc.c.vir[spin][w - q * (spin ? S.vb : S.va)] + spin;
+      uint64_t y1[NW];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) y1[k] = x[k];
+      int par = parity_below<NW>(y1, I);
+      flip<NW>(y1, I);
+      par ^= parity_below<NW>(y1, A);
+      flip<NW>(y1, A);
+      wc.T[u].drank = (int32_t)spin_rank<NW>(binom, y1, spin) - (int32_t)(spin ? rb : ra);
+      wc.T[u].info = (uint32_t)I | ((uint32_t)A << 8) | ((uint32_t)par << 16);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -89,12 +121,35 @@ __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* 
     for (uint32_t t0 = 0; t0 < S.C; t0 += 64) {
       const uint32_t t = t0 + lane;
       if (t < S.C) {
-        const Excitation e = unrank(S, wc.c, t);
-        uint64_t xo[NW];
-        const int sg = apply_excitation<NW>(x, e, xo);
-        const double val = excitation_value(S, e, wc.F, ed);
-        const int64_t idx = (int64_t)spin_rank<NW>(binom, xo, 0) * nb_dim + spin_rank<NW>(binom, xo, 1);
-        acc += (sg < 0 ? -val : val) * v[idx];
+        double val;
+        int neg;
+        int64_t idx;
+        if (t >= ab0) {
+          const uint32_t u = t - ab0, u1 = fdiv(u, S.f_nSb), u2 = S.nSa + (u - u1 * S.nSb);
+          const KpmSingle sa = wc.T[u1], sb = wc.T[u2];
+          const int I = sa.info & 0xFF, A = (sa.info >> 8) & 0xFF, J = sb.info & 0xFF, Bq = (sb.info >> 8) & 0xFF;
+          neg = (int)(((sa.info ^ sb.info) >> 16) & 1u) ^ (I < J) ^ (I < Bq) ^ (J < A) ^ (Bq < A);
+          val = S.S[((((size_t)(I >> 1) * n + (J >> 1)) * n + (A >> 1)) * n) + (Bq >> 1)];
+          idx = (int64_t)((int64_t)ra + sa.drank) * nb_dim + ((int64_t)rb + sb.drank);
+        } else if (t >= 1u && t < 1u + nS) {
+          const uint32_t u = t - 1u;
+          const KpmSingle sg = wc.T[u];
+          neg = (int)((sg.info >> 16) & 1u);
+          val = wc.F[u];
+          idx = u < S.nSa ? ((int64_t)ra + sg.drank) * nb_dim + rb : (int64_t)ra * nb_dim + ((int64_t)rb + sg.drank);
+        } else if (t == 0u) {
+          neg = 0;
+          val = ed;
+          idx = r;
+        } else {   // same-spin double: only that spin's set changes
+          const Excitation e = unrank(S, wc.c, t);
+          uint64_t xo[NW];
+          neg = apply_excitation<NW>(x, e, xo) < 0;
+          val = excitation_value(S, e, wc.F, ed);
+          idx = e.spin == 0 ? (int64_t)spin_rank<NW>(binom, xo, 0) * nb_dim + rb
+                            : (int64_t)ra * nb_dim + spin_rank<NW>(binom, xo, 1);
+        }
+        acc += (neg ? -val : val) * v[idx];
       }
     }
 #pragma unroll
@@ -226,7 +281,8 @@ hipError_t launch_sector_apply(const SysDev& S, const uint32_t* binom, int64_t d
                                unsigned grid, hipStream_t st) {
   if (dim <= 0) return hipSuccess;
   const uint32_t nS = S.nSa + S.nSb;
-  const uint32_t wstride = (uint32_t)((sizeof(SampleCtx) + 8u * (nS ? nS : 1u) + 15u) & ~15u);
+  // per wave: SampleCtx, nS single values (8 B), nS table rows (8 B)
+  const uint32_t wstride = (uint32_t)((sizeof(SampleCtx) + 16u * (nS ? nS : 1u) + 15u) & ~15u);
   const size_t lds = 4u * wstride;
   if (lds > 65536) {
     auto kern = (S.W == 1) ? (const void*)k_sector_apply<1> : (const void*)k_sector_apply<2>;
