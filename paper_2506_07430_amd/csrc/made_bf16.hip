@@ -282,6 +282,51 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
         a1[0] = a1[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
         const bf16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
         const bf16x8* w1p = w0p + (size_t)nk * 64;
+        if constexpr (lds_partial_bf16<HMAX>() && NT == 2) {
+          // hidden weights from global memory (one wave per SIMD): a pair's loads are issued
+          // in chunks of CH k-blocks, one chunk ahead of the products (the three-term mode has
+          // no registers left for this)
+          constexpr int CH = 4, NC = KB / CH;
+          bf16x8 w0b[NC][CH], w1b[NC][CH];
+#pragma unroll
+          for (int c = 0; c < 1 && c < NC; ++c)   // prologue: chunk 0
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+              const int kb = c * CH + j;
+              if (kb == 0 || kb < ke1) w1b[c][j] = w1p[kb * 64];
+              if (kb == 0 || kb < ke0) w0b[c][j] = w0p[kb * 64];
+            }
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (c * CH < ke1) {
+              if (c + 1 < NC) {
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                  const int kb = (c + 1) * CH + j;
+                  if (kb < ke1) w1b[c + 1][j] = w1p[kb * 64];
+                  if (kb < ke0) w0b[c + 1][j] = w0p[kb * 64];
+                }
+              }
+#pragma unroll
+              for (int j = 0; j < CH; ++j) {
+                const int kb = c * CH + j;
+                if (kb == 0 || kb < ke1) {
+#pragma unroll
+                  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                    for (int i = 0; i < NT; ++i) a1[cc] = mfma_bf16(w1b[c][j], act[i][cc][kb], a1[cc]);
+                  if (kb == 0 || kb < ke0) {
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                      for (int i = 0; i < NT; ++i) a0[cc] = mfma_bf16(w0b[c][j], act[i][cc][kb], a0[cc]);
+                  }
+                }
+              }
+            }
+          }
+        } else {
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           if (kb == 0 || kb < ke1) {
@@ -298,6 +343,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
                 for (int i = 0; i < NT; ++i) a0[c] = mfma_bf16(w0, act[i][c][kb], a0[c]);
             }
           }
+        }
         }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
