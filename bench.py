@@ -87,8 +87,8 @@ def main():
                          "for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
-              "(DESIGN.md), not a measured path in this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the local-energy path would shard "
+              "over samples, but only the one-GPU path is implemented and timed.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -447,7 +447,7 @@ hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st) {
 template <int HMAX, int NW>
 static hipError_t eval_f64_nw(const EvalArgs& A, unsigned grid, hipStream_t st) {
   constexpr size_t kLds = 160 * 1024;
-  static size_t static_lds = ~(size_t)0;   // the same on every device of this build
+  static size_t static_lds = ~(size_t)0;   // a property of the code object: the same on every device
   if (static_lds == ~(size_t)0) {
     hipFuncAttributes fa;
     const hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_eval_f64<HMAX, NW, true>);
