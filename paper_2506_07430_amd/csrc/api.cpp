@@ -652,9 +652,9 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
   size_t wmax = 0, bmax = 0;
   for (int s = 0; s < n_sys; ++s) {
-    uint32_t l0;
-    wmax = std::max(wmax, staged_wbytes(M.G[s], M.hmax, &l0));
-    M.l0[s] = l0;
+    M.l0[s] = 0;
+    if (M.precision != ELOCAL_BF16) continue;
+    wmax = std::max(wmax, staged_wbytes(M.G[s], M.hmax, &M.l0[s]));
     bmax = std::max(bmax, align256(M.G[s].bbytes));
   }
   if (M.precision == ELOCAL_BF16) {
