@@ -73,8 +73,14 @@ hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_we
 // Waves per block of the BF16 fused kernels (single and multi-system), one block per CU:
 // two waves per SIMD while the activations (nterms bf16 terms of 32 rows x hmax units,
 // this layer's and the next) fit in 256 registers, else one (with 512 registers).
-constexpr int eval_waves_bf16(int hmax, int nterms) { return hmax * nterms <= 256 ? 8 : 4; }
-constexpr int kMaxEvalWavesBF16 = 8;
+// 16-row tiles per pass of the network: one up to width 128 with two terms (so that a wave
+// needs at most 128 registers and four waves share a SIMD: their VALU and MFMA work then
+// overlap), else two.
+constexpr int eval_cols_bf16(int hmax, int nterms) { return (hmax <= 128 && nterms == 2) ? 1 : 2; }
+constexpr int eval_waves_bf16(int hmax, int nterms) {
+  return eval_cols_bf16(hmax, nterms) == 1 ? 16 : hmax * nterms <= 256 ? 8 : 4;
+}
+constexpr int kMaxEvalWavesBF16 = 16;
 // Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists and
 // the FP64 suffix sums of its per-orbital log2 probabilities.
 constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(double);

@@ -194,19 +194,21 @@ __device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsig
 }
 
 // Output block ob of the last layer for both column blocks (rows r and 16 + r).
-template <int KB, int NT>
+template <int KB, int NT, int NC>
 __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ WL,
-                                          const float* __restrict__ bias, const bf16x8 (&act)[NT][2][KB],
-                                          int ob, int lane, f32x4 (&a)[2]) {
+                                          const float* __restrict__ bias, const bf16x8 (&act)[NT][NC][KB],
+                                          int ob, int lane, f32x4 (&a)[NC]) {
   const int l = M.L, nk = M.nk[l], ke = sgpr(M.kend[l][ob]);
-  a[0] = a[1] = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
+  const f32x4 b4 = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
+#pragma unroll
+  for (int c = 0; c < NC; ++c) a[c] = b4;
   const bf16x8* wp = WL + (size_t)(ob * nk) * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     if (kb == 0 || kb < ke) {
       const bf16x8 w = wp[kb * 64];
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int i = 0; i < NT; ++i) a[c] = mfma_bf16(w, act[i][c][kb], a[c]);
     }
@@ -219,20 +221,20 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __rest
 // terms (one MFMA per term and weight fragment).
 // With XLUT the layer-0 operands come from the LDS table xlut (kXLutBytes), else they are
 // expanded from the bits in registers.
-template <int HMAX, int NW, int NT, bool XLUT = false, class Epi>
+template <int HMAX, int NW, int NT, int NC, bool XLUT = false, class Epi>
 __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt,
                                          const float* __restrict__ bias,
-                                         const uint64_t (&xr)[2][NW], int lane, int ob_first,
+                                         const uint64_t (&xr)[NC][NW], int lane, int ob_first,
                                          const bf16x8* xlut, Epi&& epi) {
   constexpr int KB = HMAX / 32;
   const int g = lane >> 4;
-  bf16x8 act[NT][2][KB];
+  bf16x8 act[NT][NC][KB];
   // ---- layer 0: exact 0/1 inputs, one MFMA per fragment
   {
     const int nk = M.nk[0], nob = M.nob[0];
-    bf16x8 xin[2][4];
+    bf16x8 xin[NC][4];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
         if (XLUT) xin[c][kb] = xlut[kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u];
@@ -241,26 +243,30 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
         const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
-        f32x4 a0[2], a1[2];
-        a0[0] = a0[1] = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
-        a1[0] = a1[1] = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
+        f32x4 a0[NC], a1[NC];
+        {
+          const f32x4 b0 = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
+          const f32x4 b1 = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
+        }
         const bf16x8* w0p = Wt.l0 + (size_t)((2 * kbo) * nk) * 64 + lane;
         const bf16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
           if (kb == 0 || kb < ke1) {
             const bf16x8 w1 = w1p[kb * 64];
-            a1[0] = mfma_bf16(w1, xin[0][kb], a1[0]);
-            a1[1] = mfma_bf16(w1, xin[1][kb], a1[1]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a1[c] = mfma_bf16(w1, xin[c][kb], a1[c]);
             if (kb == 0 || kb < ke0) {
               const bf16x8 w0 = w0p[kb * 64];
-              a0[0] = mfma_bf16(w0, xin[0][kb], a0[0]);
-              a0[1] = mfma_bf16(w0, xin[1][kb], a0[1]);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) a0[c] = mfma_bf16(w0, xin[c][kb], a0[c]);
             }
           }
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
           bf16x8 t[NT];
           split_relu<NT>(a0[c], a1[c], t);
 #pragma unroll
@@ -272,24 +278,28 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
   // ---- hidden layers 1..L-1
   for (int l = 1; l < M.L; ++l) {
     const int nk = M.nk[l], nob = M.nob[l];
-    bf16x8 nxt[NT][2][KB];
+    bf16x8 nxt[NT][NC][KB];
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
         const int ke0 = sgpr(M.kend[l][2 * kbo]), ke1 = sgpr(M.kend[l][2 * kbo + 1]);
-        f32x4 a0[2], a1[2];
-        a0[0] = a0[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
-        a1[0] = a1[1] = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
+        f32x4 a0[NC], a1[NC];
+        {
+          const f32x4 b0 = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
+          const f32x4 b1 = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
+        }
         const bf16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
         const bf16x8* w1p = w0p + (size_t)nk * 64;
         if constexpr (lds_partial_bf16<HMAX>() && NT == 2) {
           // hidden weights from global memory (one wave per SIMD): a pair's loads are issued
           // in chunks of CH k-blocks, one chunk ahead of the products (the three-term mode has
           // no registers left for this)
-          constexpr int CH = 4, NC = KB / CH;
-          bf16x8 w0b[NC][CH], w1b[NC][CH];
+          constexpr int CH = 4, NCH = KB / CH;
+          bf16x8 w0b[NCH][CH], w1b[NCH][CH];
 #pragma unroll
-          for (int c = 0; c < 1 && c < NC; ++c)   // prologue: chunk 0
+          for (int c = 0; c < 1 && c < NCH; ++c)   // prologue: chunk 0
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
               const int kb = c * CH + j;
@@ -297,10 +307,10 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
               if (kb == 0 || kb < ke0) w0b[c][j] = w0p[kb * 64];
             }
 #pragma unroll
-          for (int c = 0; c < NC; ++c) {
+          for (int c = 0; c < NCH; ++c) {
             __builtin_amdgcn_sched_barrier(0);
             if (c * CH < ke1) {
-              if (c + 1 < NC) {
+              if (c + 1 < NCH) {
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
                   const int kb = (c + 1) * CH + j;
@@ -313,12 +323,12 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
                 const int kb = c * CH + j;
                 if (kb == 0 || kb < ke1) {
 #pragma unroll
-                  for (int cc = 0; cc < 2; ++cc)
+                  for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                     for (int i = 0; i < NT; ++i) a1[cc] = mfma_bf16(w1b[c][j], act[i][cc][kb], a1[cc]);
                   if (kb == 0 || kb < ke0) {
 #pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
+                    for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                       for (int i = 0; i < NT; ++i) a0[cc] = mfma_bf16(w0b[c][j], act[i][cc][kb], a0[cc]);
                   }
@@ -332,13 +342,13 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
           if (kb == 0 || kb < ke1) {
             const bf16x8 w1 = w1p[kb * 64];
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
               for (int i = 0; i < NT; ++i) a1[c] = mfma_bf16(w1, act[i][c][kb], a1[c]);
             if (kb == 0 || kb < ke0) {
               const bf16x8 w0 = w0p[kb * 64];
 #pragma unroll
-              for (int c = 0; c < 2; ++c)
+              for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int i = 0; i < NT; ++i) a0[c] = mfma_bf16(w0, act[i][c][kb], a0[c]);
             }
@@ -346,7 +356,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
         }
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
           bf16x8 t[NT];
           split_relu<NT>(a0[c], a1[c], t);
 #pragma unroll
@@ -357,7 +367,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
     for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) act[i][c][kb] = nxt[i][c][kb];
   }
@@ -366,9 +376,9 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
     const int nob = M.nob[M.L];
 #pragma unroll 1
     for (int ob = sgpr(ob_first); ob < nob; ++ob) {
-      f32x4 acc[2];
-      out_block<KB, NT>(M, Wt.out, bias, act, ob, lane, acc);
-      epi(ob, acc[0], acc[1]);
+      f32x4 acc[NC];
+      out_block<KB, NT, NC>(M, Wt.out, bias, act, ob, lane, acc);
+      epi(ob, acc);
     }
   }
 }
@@ -489,18 +499,18 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
   RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], min(g, n - 1)), cursor_at<NW>(xr[1], min(g, n - 1))};
-  mlp_bf16<HMAX, NW, NT>(M, Wt, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4& a0, const f32x4& a1) {
+  mlp_bf16<HMAX, NW, NT, 2>(M, Wt, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4 (&a)[2]) {
     const int p = 4 * ob + g;
     if (p < n - 1) {   // the last orbital's conditional is 1
       const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
+        const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, a[c]);
         A[c] += (double)lp;
         if (rb[c] < Bn) P.lpx[rb[c] * n + p] = lp;     // log2 units
       }
     }
-    if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
+    if (ob == ob_phi && g == g_phi) { zp[0] = a[0][0]; zp[1] = a[1][0]; }
   });
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -585,6 +595,7 @@ template <int HMAX, int NW, int NT, class Gen = ScGen>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsBF16& Wt,
                                                const float* __restrict__ bias, const bf16x8* xlut,
                                                WaveCtxBF16& wc, int64_t item, SampleState<NW>& st, int lane) {
+  constexpr int NC = eval_cols_bf16(HMAX, NT);
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
   const int g = lane >> 4, r16 = lane & 15;
@@ -634,46 +645,61 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
     const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
     double dA_own = 0.0;
     float zp_own = 0.f;
-    // ---- network on entries 32h .. 32h + 31 (not unrolled: one copy of the network code)
+    // ---- network on entries 16 NC h .. 16 NC (h + 1) - 1 (not unrolled: one copy of the
+    // network code)
 #pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-      uint64_t xr[2][NW];
-      int p0[2];
+    for (int h = 0; h < 4 / NC; ++h) {
+      uint64_t xr[NC][NW];
+      int p0[NC];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int src = 32 * h + 16 * c + r16;
+      for (int c = 0; c < NC; ++c) {
+        const int src = 16 * NC * h + 16 * c + r16;
 #pragma unroll
         for (int w = 0; w < NW; ++w) xr[c][w] = __shfl(xo[w], src);
         p0[c] = __shfl(p0o, src);
       }
-      double dA[2] = {0.0, 0.0};
-      float zp[2] = {0.f, 0.f};
+      double dA[NC];
+      float zp[NC];
+      RowCursor<NW> rc[NC];
       const int pfirst = min(4 * ob_first + g, n - 1);
-      RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], pfirst), cursor_at<NW>(xr[1], pfirst)};
-      mlp_bf16<HMAX, NW, NT, true>(M, Wt, bias, xr, lane, ob_first, xlut, [&](int ob, const f32x4& a0, const f32x4& a1) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        dA[c] = 0.0;
+        zp[c] = 0.f;
+        rc[c] = cursor_at<NW>(xr[c], pfirst);
+      }
+      mlp_bf16<HMAX, NW, NT, NC, true>(M, Wt, bias, xr, lane, ob_first, xlut, [&](int ob, const f32x4 (&a)[NC]) {
         const int p = 4 * ob + g;
         if (p < n - 1) {   // the last orbital's conditional is 1
           const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, c ? a1 : a0);
+          for (int c = 0; c < NC; ++c) {
+            const float lp = cond_log2p_step<NW>(rc[c], ta, tb, na, nb, a[c]);
             float d = p >= p0[c] ? lp : 0.f;
             asm volatile("" : "+v"(d));   // keeps the select in 32 bits (before the convert)
             dA[c] += (double)d;     // sum over p >= p0 of log2 p(x'); x's part is subtracted below
           }
         }
-        if (ob == ob_phi && g == g_phi) { zp[0] = a0[0]; zp[1] = a1[0]; }
+        if (ob == ob_phi && g == g_phi) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) zp[c] = a[c][0];
+        }
       });
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < NC; ++c) {
         dA[c] += __shfl_xor(dA[c], 16);
         dA[c] += __shfl_xor(dA[c], 32);
         zp[c] = __shfl(zp[c], g_phi * 16 + r16);
       }
-      if ((lane >> 5) == h) {
-        const int c = (lane >> 4) & 1;
-        dA_own = (c ? dA[1] : dA[0]) - wc.sfx[p0o];
-        zp_own = c ? zp[1] : zp[0];
+      if (lane / (16 * NC) == h) {
+        const int c = (lane >> 4) % NC;
+        double dsel = dA[0];
+        float zsel = zp[0];
+#pragma unroll
+        for (int cc = 1; cc < NC; ++cc)
+          if (c == cc) { dsel = dA[cc]; zsel = zp[cc]; }
+        dA_own = dsel - wc.sfx[p0o];
+        zp_own = zsel;
       }
     }
     // ---- FP64 ratio and accumulation, one entry per lane (an entry with H = 0 adds
