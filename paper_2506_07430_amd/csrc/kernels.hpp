@@ -70,15 +70,15 @@ hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t
 hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, size_t lds_bytes,
                             unsigned grid, hipStream_t st);
 
-// Waves per block of the BF16 fused kernels (single and multi-system), one block per CU:
-// two waves per SIMD while the activations (nterms bf16 terms of 32 rows x hmax units,
-// this layer's and the next) fit in 256 registers, else one (with 512 registers).
-// 16-row tiles per pass of the network: one up to width 128 with two terms (so that a wave
-// needs at most 128 registers and four waves share a SIMD: their VALU and MFMA work then
-// overlap), else two.
-constexpr int eval_cols_bf16(int hmax, int nterms) { return (hmax <= 128 && nterms == 2) ? 1 : 2; }
+// Shape of the BF16 fused kernels (single and multi-system), one block per CU. With two
+// bf16 terms per activation a pass of the network takes one 16-row tile, so that a wave
+// fits in 128 registers up to width 128 (16 waves per block, four per SIMD) and in 256 at
+// width 256 (8 waves, two per SIMD): the VALU and MFMA work of different waves on a SIMD
+// overlap the more waves share it. Three terms take two tiles per pass (8 waves up to
+// hmax * nterms = 256, else 4).
+constexpr int eval_cols_bf16(int hmax, int nterms) { return nterms == 2 ? 1 : 2; }
 constexpr int eval_waves_bf16(int hmax, int nterms) {
-  return eval_cols_bf16(hmax, nterms) == 1 ? 16 : hmax * nterms <= 256 ? 8 : 4;
+  return eval_cols_bf16(hmax, nterms) == 1 ? (hmax <= 128 ? 16 : 8) : hmax * nterms <= 256 ? 8 : 4;
 }
 constexpr int kMaxEvalWavesBF16 = 16;
 // Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists and
