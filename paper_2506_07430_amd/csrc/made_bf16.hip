@@ -591,6 +591,21 @@ struct PauliGen {
   }
 };
 
+// H exp(dA ln2 / 2 + i 2 pi (sigmoid(zp) - sig_x)) in FP64. The phase difference 2 pi d has
+// |d| < 1, so sincospi needs no large-argument reduction; the magnitude with dA in log2
+// units is exp2(dA / 2). Not inlined (nor is the sample's sigmoid): inlined, the compiler
+// keeps the constants of the FP64 functions in registers across the whole kernel, and at
+// four waves per SIMD they spill to scratch memory.
+__device__ __attribute__((noinline)) double sigmoid64(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+__device__ __attribute__((noinline)) double2 ratio_term(double hv, float zp, double sig_x, double dA) {
+  const double d = 1.0 / (1.0 + exp(-(double)zp)) - sig_x;
+  double sn, cs;
+  sincospi(2.0 * d, &sn, &cs);
+  const double mag = hv * exp2(0.5 * dA);
+  return make_double2(mag * cs, mag * sn);
+}
+
 template <int HMAX, int NW, int NT, class Gen = ScGen>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsBF16& Wt,
                                                const float* __restrict__ bias, const bf16x8* xlut,
@@ -620,7 +635,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
       if (lane == 0) wc.sfx[n] = 0.0;
     }
     wave_sync_lds();
-    st.sig_x = 1.0 / (1.0 + exp(-P.zphi[b]));
+    st.sig_x = sigmoid64(P.zphi[b]);
     st.ed = P.ediag[b];
     st.Fs = P.F + (size_t)b * (S.nSa + S.nSb);
     st.b = b;
@@ -705,14 +720,9 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
     // ---- FP64 ratio and accumulation, one entry per lane (an entry with H = 0 adds
     // nothing; skipping it also keeps an infinite ratio of a zero-amplitude x' out)
     if (t < len && hv != 0.0) {
-      // phase difference 2 pi d with |d| < 1: sincospi needs no large-argument reduction;
-      // the magnitude exp(dA ln2 / 2) with dA in log2 units is exp2(dA / 2)
-      const double d = 1.0 / (1.0 + exp(-(double)zp_own)) - st.sig_x;
-      double sn, cs;
-      sincospi(2.0 * d, &sn, &cs);
-      const double mag = hv * exp2(0.5 * dA_own);
-      acc_re += mag * cs;
-      acc_im += mag * sn;
+      const double2 r = ratio_term(hv, zp_own, st.sig_x, dA_own);
+      acc_re += r.x;
+      acc_im += r.y;
     }
   }
 #pragma unroll
