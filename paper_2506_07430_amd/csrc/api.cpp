@@ -255,7 +255,7 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
   if (G.precision == ELOCAL_BF16) {
     p.lds_w = staged_wbytes(G, G.hmax, &p.lds_l0);
     const size_t need = p.lds_w + align256(G.bbytes) + kCtxBytesBF16;
-    p.ldsw = need <= kLdsBytes;   // one 8-wave block per CU owns the CU's LDS
+    p.ldsw = need <= kLdsBytes;   // one block per CU owns the CU's LDS
     p.lds = p.ldsw ? need : kCtxBytesBF16;
     p.waves = eval_waves_bf16(G.hmax, G.nterms);
   } else {

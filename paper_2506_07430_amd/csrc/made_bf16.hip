@@ -293,7 +293,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
         const bf16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
         const bf16x8* w1p = w0p + (size_t)nk * 64;
         if constexpr (lds_partial_bf16<HMAX>() && NT == 2) {
-          // hidden weights from global memory (one wave per SIMD): a pair's loads are issued
+          // hidden weights from global memory (few waves per SIMD): a pair's loads are issued
           // in chunks of CH k-blocks, one chunk ahead of the products (the three-term mode has
           // no registers left for this)
           constexpr int CH = 4, NCH = KB / CH;
