@@ -105,6 +105,32 @@ __device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke,
   }
 }
 
+// As kloop_f64 for a block whose k-range is whole chunks (ke a multiple of CH, at most the
+// block's stored k-steps): one branch per chunk instead of one per k-step.
+template <int KSMAX, int CH, class F>
+__device__ __forceinline__ void kloop_f64_whole(const double* __restrict__ wp, int ke, F&& f) {
+  constexpr int LA = 2, NC = (KSMAX + CH - 1) / CH;
+  double w[NC][CH];
+#pragma unroll
+  for (int c = 0; c < LA && c < NC; ++c)
+    if (c * CH < ke) {
+#pragma unroll
+      for (int j = 0; j < CH; ++j) w[c][j] = wp[(c * CH + j) * 64];
+    }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (c * CH < ke) {
+      if (c + LA < NC && (c + LA) * CH < ke) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) w[c + LA][j] = wp[((c + LA) * CH + j) * 64];
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) f(c * CH + j, w[c][j]);
+    }
+  }
+}
+
 // Network on one 16-row block (row r of lane r); epi(ob, acc) per output block.
 // W: packed weights (layer l at fragment woff[l]); WL: the output layer's fragment 0,
 // which may be a copy in LDS.
@@ -150,7 +176,10 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
         const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
-        kloop_f64<KS, KCH>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+        // whole chunks: the extra k-steps up to a chunk boundary hold masked (zero) weights,
+        // and nk (width / 4, widths are multiples of 32) is a multiple of the chunk
+        const int kw = min(nk, (ke + KCH - 1) / KCH * KCH);
+        kloop_f64_whole<KS, KCH>(wp, kw, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
         nxt[ob] = relu4(acc);
       }
     }
@@ -164,7 +193,8 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
       const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
       f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
       const double* wp = WL + (size_t)(ob * nk) * 64 + lane;
-      kloop_f64<KS, KCH>(wp, ke, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+      const int kw = min(nk, (ke + KCH - 1) / KCH * KCH);   // whole chunks, as above
+      kloop_f64_whole<KS, KCH>(wp, kw, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
       epi(ob, acc);
     }
   }
