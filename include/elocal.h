@@ -333,8 +333,9 @@ elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launch
 /*
  * Launch shape of the fused local-energy kernel (for the autotuner). A value <= 0
  * restores the built-in choice. ELOCAL_TUNE_GRID: blocks of the persistent grid-stride
- * loop over work items (a block has 8 waves in BF16 mode up to hidden width 128, 4
- * otherwise; elocal_eval_multi takes it from its first handle); ELOCAL_TUNE_GROUPS:
+ * loop over work items (a block has 16 waves in BF16 mode up to hidden width 128 with
+ * two terms per activation, fewer for wider networks or three terms; elocal_eval_multi
+ * takes it from its first handle); ELOCAL_TUNE_GROUPS:
  * list-entry groups per work
  * item (64 entries per group in BF16 mode, 16 in FP64 mode). Results do not depend on
  * the launch shape except through the fixed per-item summation order (rounding only).

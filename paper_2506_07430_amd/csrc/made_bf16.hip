@@ -193,7 +193,7 @@ __device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsig
   return {S, S, S + (size_t)M.woff[M.L] * 64};
 }
 
-// Output block ob of the last layer for both column blocks (rows r and 16 + r).
+// Output block ob of the last layer for the NC 16-row tiles (tile c: row r of lane r).
 template <int KB, int NT, int NC>
 __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ WL,
                                           const float* __restrict__ bias, const bf16x8 (&act)[NT][NC][KB],
@@ -215,8 +215,8 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __rest
   }
 }
 
-// Runs the network on two 16-row column blocks (rows r and 16 + r of lane r) and calls
-// epi(ob, acc_c0, acc_c1) for the output blocks ob >= ob_first (earlier blocks belong
+// Runs the network on NC 16-row tiles (tile c: row r of lane r) and calls epi(ob, a[NC])
+// for the output blocks ob >= ob_first (earlier blocks belong
 // to orbitals the caller does not need). Hidden activations are carried as NT bf16
 // terms (one MFMA per term and weight fragment).
 // With XLUT the layer-0 operands come from the LDS table xlut (kXLutBytes), else they are
@@ -547,10 +547,6 @@ struct SampleState {
   const double* Fs;
 };
 
-// One work item = one sample and P.tpi consecutive groups of 64 list entries. Per group:
-// every lane generates one entry (x', H_{x'x} in FP64, first changed orbital); the
-// network runs twice on 32 of them; every lane then forms H exp(dA + i dphi) in FP64
-// for its own entry. The item's partial sum (fixed order) goes to P.partial[item].
 // Entry generators of the fused kernel. Entry t of a sample's list (t = 0 is the sample
 // itself and is handled outside the kernel) gives x' and H_{x x'}.
 //
@@ -606,6 +602,11 @@ __device__ __attribute__((noinline)) double2 ratio_term(double hv, float zp, dou
   return make_double2(mag * cs, mag * sn);
 }
 
+// One work item = one sample and P.tpi consecutive groups of 64 list entries. Per group:
+// every lane generates one entry (x', H_{x'x} in FP64, first changed orbital); the
+// network runs in 4 / NC passes of NC 16-row tiles over the 64 entries; every lane then
+// forms H exp(dA + i dphi) in FP64 for its own entry. The item's partial sum (fixed
+// order) goes to P.partial[item].
 template <int HMAX, int NW, int NT, class Gen = ScGen>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsBF16& Wt,
                                                const float* __restrict__ bias, const bf16x8* xlut,
@@ -737,7 +738,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
 }
 
 // Block shape of the fused kernels: one block per CU, so the whole 160 KiB of LDS can
-// hold the packed weights of one ansatz; 8 waves (two per SIMD) up to width 128.
+// hold the packed weights of one ansatz (waves per block: eval_waves_bf16).
 
 // Copies the packed weights (all of them, or with PARTIAL the output layer followed, if
 // l0, by layer 0) and the biases into LDS.
