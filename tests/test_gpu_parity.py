@@ -108,7 +108,8 @@ def test_eval_fp64_c0_ansatz_samples():
 
 
 @pytest.mark.parametrize("n,na,nb,widths", [(5, 2, 1, (32,)), (12, 6, 5, (64, 32)), (33, 8, 9, (32, 32)),
-                                             (40, 14, 14, (256, 256, 256)), (7, 0, 7, (32,))])
+                                             (40, 14, 14, (256, 256, 256)), (7, 0, 7, (32,)),
+                                             (10, 4, 5, (96, 160))])
 def test_eval_fp64_shapes(n, na, nb, widths):
     p = synth.random_problem(n, na, nb, widths, seed=100 + n, n_chol=4, decay=5.0, samples=5)
     el, _, th = _eval(p, p.x, elocal.FP64)
@@ -129,11 +130,12 @@ def test_eval_bf16_c0():
 @pytest.mark.parametrize("precision", [elocal.BF16, elocal.BF16X3])
 @pytest.mark.parametrize("n,na,nb,widths", [(2, 1, 1, (32,)), (3, 1, 2, (32,)), (5, 2, 1, (32,)),
                                              (5, 0, 3, (64,)), (12, 6, 5, (64, 32)), (33, 8, 9, (32, 32)),
-                                             (17, 8, 8, (256,)), (64, 3, 2, (64,))])
+                                             (17, 8, 8, (256,)), (64, 3, 2, (64,)), (10, 4, 5, (96, 160))])
 def test_eval_bf16_shapes(n, na, nb, widths, precision):
     """Shapes at the packing's edges: a single orbital with logits (n = 2), the phase row
     alone in an output block (n = 5), an empty spin block, the word boundary (n = 33),
-    the width-256 kernels and the largest n; local energies and log psi of samples drawn
+    the width-256 kernels, the largest n and widths that are not powers of two (96, 160:
+    odd numbers of weight chunks); local energies and log psi of samples drawn
     from the ansatz (uniformly drawn determinants of the sparse 64-orbital sector have
     ratios psi(x')/psi(x) up to e^21, whose FP32 log-softmax rounding alone exceeds the bar)."""
     p = synth.random_problem(n, na, nb, widths, seed=300 + n + na, n_chol=4, decay=5.0, samples=1)
