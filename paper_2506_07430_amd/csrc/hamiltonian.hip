@@ -53,9 +53,44 @@ __global__ void __launch_bounds__(256) k_prep(SysDev S, const uint64_t* __restri
   if (lane == 0) ediag[b] = e;
 }
 
-// One thread per list entry: unrank, apply the operators, look up the value, store.
+// One list entry: x' = the excitation applied to x, H_{x x'} with its sign, the sign, and the
+// four spin-orbitals of the excitation (0xFF for unused slots), one byte each.
+template <int NW>
+struct ListEntry {
+  uint64_t y[NW];
+  double h;
+  int8_t sg;
+  uint32_t code;
+};
+
+template <int NW>
+__device__ __forceinline__ ListEntry<NW> list_entry(const SysDev& S, const SampleCtx& c, const uint64_t (&xv)[NW],
+                                                    const double* Fs, double ed, uint32_t t) {
+  ListEntry<NW> r;
+  const Excitation e = unrank(S, c, t);
+  const int sg = apply_excitation<NW>(xv, e, r.y);
+  const double v = excitation_value(S, e, Fs, ed);
+  r.h = sg < 0 ? -v : v;
+  r.sg = (int8_t)sg;
+  r.code = (uint32_t)(e.I < 0 ? 0xFF : e.I) | ((uint32_t)(e.J < 0 ? 0xFF : e.J) << 8) |
+           ((uint32_t)(e.A < 0 ? 0xFF : e.A) << 16) | ((uint32_t)(e.Bq < 0 ? 0xFF : e.Bq) << 24);
+  return r;
+}
+
 // The four output streams are written with nontemporal stores: they are consumed later,
 // and allocating them in L2 would evict the integral tables every entry reads.
+template <int NW>
+__device__ __forceinline__ void store_entry(const ListEntry<NW>& r, size_t o, uint64_t* __restrict__ xp,
+                                            double* __restrict__ hval, int8_t* __restrict__ sign,
+                                            uint32_t* __restrict__ exc) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) __builtin_nontemporal_store(r.y[w], xp + o * NW + w);
+  __builtin_nontemporal_store(r.h, hval + o);
+  __builtin_nontemporal_store(r.sg, sign + o);
+  __builtin_nontemporal_store(r.code, exc + o);
+}
+
+// One thread per list entry, scalar stores (outputs of any alignment).
 template <int NW>
 __global__ void __launch_bounds__(256) k_connect(SysDev S, const uint64_t* __restrict__ x,
                                                  int64_t B, uint32_t chunks,
@@ -72,19 +107,73 @@ __global__ void __launch_bounds__(256) k_connect(SysDev S, const uint64_t* __res
   __syncthreads();
   const uint32_t t = chunk * 256u + threadIdx.x;
   if (t >= S.C) return;
-  const Excitation e = unrank(S, c, t);
-  uint64_t y[NW];
-  const int sg = apply_excitation<NW>(xv, e, y);
-  const uint32_t nS = S.nSa + S.nSb;
-  const double v = excitation_value(S, e, F + (size_t)b * nS, ediag[b]);
-  const size_t o = (size_t)b * S.C + t;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) __builtin_nontemporal_store(y[w], xp + o * NW + w);
-  __builtin_nontemporal_store(sg < 0 ? -v : v, hval + o);
-  __builtin_nontemporal_store((int8_t)sg, sign + o);
-  const uint32_t code = (uint32_t)(e.I < 0 ? 0xFF : e.I) | ((uint32_t)(e.J < 0 ? 0xFF : e.J) << 8) |
-                        ((uint32_t)(e.A < 0 ? 0xFF : e.A) << 16) | ((uint32_t)(e.Bq < 0 ? 0xFF : e.Bq) << 24);
-  __builtin_nontemporal_store(code, exc + o);
+  const ListEntry<NW> r = list_entry<NW>(S, c, xv, F + (size_t)b * (S.nSa + S.nSb), ediag[b], t);
+  store_entry<NW>(r, (size_t)b * S.C + t, xp, hval, sign, exc);
+}
+
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Two consecutive entries per thread, stored as one vector per stream (16 B of x' per word
+// and of H, 8 B of codes, 2 B of signs), over the flat entry index o = b C + t: block k
+// takes entries [512 k, 512 k + 512), so every wave writes whole, aligned pieces of each
+// stream, which the memory system takes at a much higher rate than one entry per thread
+// over per-sample blocks (whose pieces start at arbitrary offsets b C). With C >= 512 a
+// block spans at most two samples; waves 0 and 1 build their contexts. A pair starts at an
+// even o, so with outputs aligned to 16 (x', H), 8 (codes) and 2 (signs) bytes every vector
+// store is naturally aligned.
+template <int NW>
+__device__ __forceinline__ ListEntry<NW> flat_entry(const SysDev& S, const SampleCtx (&c)[2], int64_t b0,
+                                                    const uint64_t* __restrict__ x, const double* __restrict__ ediag,
+                                                    const double* __restrict__ F, size_t o) {
+  const int64_t b = b0 + (o >= (size_t)(b0 + 1) * S.C ? 1 : 0);
+  const uint32_t t = (uint32_t)(o - (size_t)b * S.C);
+  uint64_t xv[NW];
+  load_x<NW>(x, b, xv);
+  return list_entry<NW>(S, c[b - b0], xv, F + (size_t)b * (S.nSa + S.nSb), ediag[b], t);
+}
+
+template <int NW>
+__global__ void __launch_bounds__(256) k_connect_flat(SysDev S, const uint64_t* __restrict__ x, int64_t B,
+                                                      const double* __restrict__ ediag,
+                                                      const double* __restrict__ F,
+                                                      uint64_t* __restrict__ xp, double* __restrict__ hval,
+                                                      int8_t* __restrict__ sign, uint32_t* __restrict__ exc) {
+  __shared__ SampleCtx c[2];
+  const size_t E = (size_t)B * S.C;
+  const size_t o0 = (size_t)blockIdx.x * 512u;
+  const int64_t b0 = (int64_t)(o0 / S.C);
+  const int wid = threadIdx.x >> 6;
+  if (wid < 2 && b0 + wid < B) {
+    uint64_t xv[NW];
+    load_x<NW>(x, b0 + wid, xv);
+    build_ctx<NW>(S, xv, c[wid], threadIdx.x & 63);
+  }
+  __syncthreads();
+  const size_t o = o0 + 2u * threadIdx.x;   // even
+  if (o >= E) return;
+  const ListEntry<NW> r0 = flat_entry<NW>(S, c, b0, x, ediag, F, o);
+  if (o + 1u >= E) {
+    store_entry<NW>(r0, o, xp, hval, sign, exc);
+    return;
+  }
+  const ListEntry<NW> r1 = flat_entry<NW>(S, c, b0, x, ediag, F, o + 1u);
+  static_assert(NW == 1 || NW == 2, "one or two words per determinant");
+  if constexpr (NW == 1) {
+    const u64x2 y = {r0.y[0], r1.y[0]};
+    __builtin_nontemporal_store(y, (u64x2*)(xp + o));
+  } else {
+    const u64x2 y0 = {r0.y[0], r0.y[1]}, y1 = {r1.y[0], r1.y[1]};
+    __builtin_nontemporal_store(y0, (u64x2*)(xp + o * NW));
+    __builtin_nontemporal_store(y1, (u64x2*)(xp + o * NW + NW));
+  }
+  const f64x2 h = {r0.h, r1.h};
+  __builtin_nontemporal_store(h, (f64x2*)(hval + o));
+  const uint16_t sg2 = (uint16_t)((uint8_t)r0.sg | ((uint16_t)(uint8_t)r1.sg << 8));   // byte o = entry o
+  __builtin_nontemporal_store(sg2, (uint16_t*)(sign + o));
+  const u32x2 cd = {r0.code, r1.code};
+  __builtin_nontemporal_store(cd, (u32x2*)(exc + o));
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -132,13 +221,26 @@ hipError_t launch_connect(const SysDev& S, const uint64_t* x, int64_t B, const d
                           const double* F, uint64_t* xp, double* hval, int8_t* sign, uint32_t* exc,
                           hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  const uint32_t chunks = (S.C + 255u) / 256u;
-  const uint64_t blocks = (uint64_t)B * chunks;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  if (S.W == 1)
-    hipLaunchKernelGGL(k_connect<1>, dim3((unsigned)blocks), dim3(256), 0, st, S, x, B, chunks, ediag, F, xp, hval, sign, exc);
-  else
-    hipLaunchKernelGGL(k_connect<2>, dim3((unsigned)blocks), dim3(256), 0, st, S, x, B, chunks, ediag, F, xp, hval, sign, exc);
+  // the flat paired kernel needs outputs aligned to 16 (x', H), 8 (codes) and 2 (signs)
+  // bytes, and lists of at least 512 entries (a block then spans at most two samples)
+  const bool flat = S.C >= 512u && ((uintptr_t)xp % 16u == 0) && ((uintptr_t)hval % 16u == 0) &&
+                    ((uintptr_t)exc % 8u == 0) && ((uintptr_t)sign % 2u == 0);
+  if (flat) {
+    const uint64_t blocks = ((uint64_t)B * S.C + 511u) / 512u;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (S.W == 1)
+      hipLaunchKernelGGL(k_connect_flat<1>, dim3((unsigned)blocks), dim3(256), 0, st, S, x, B, ediag, F, xp, hval, sign, exc);
+    else
+      hipLaunchKernelGGL(k_connect_flat<2>, dim3((unsigned)blocks), dim3(256), 0, st, S, x, B, ediag, F, xp, hval, sign, exc);
+  } else {
+    const uint32_t chunks = (S.C + 255u) / 256u;
+    const uint64_t blocks = (uint64_t)B * chunks;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (S.W == 1)
+      hipLaunchKernelGGL(k_connect<1>, dim3((unsigned)blocks), dim3(256), 0, st, S, x, B, chunks, ediag, F, xp, hval, sign, exc);
+    else
+      hipLaunchKernelGGL(k_connect<2>, dim3((unsigned)blocks), dim3(256), 0, st, S, x, B, chunks, ediag, F, xp, hval, sign, exc);
+  }
   return hipGetLastError();
 }
 

@@ -70,6 +70,34 @@ def test_connect_edge_shapes(n, na, nb):
     assert_connect_equal(ham, p, p.x)
 
 
+def test_connect_unaligned_outputs():
+    """Outputs that start one element into their allocation (x' and H at 8-byte, codes at
+    4-byte, signs at odd byte addresses) take the one-entry-per-thread path, aligned ones
+    the paired path over the flat entry index; both give the oracle's list, entry for
+    entry."""
+    p = synth.make_problem(1, samples=3)   # 3 x 29737 entries: an odd total, the last one unpaired
+    ham = make_ham(p)
+    x = words_to_dev(p.x)
+    B, C, W = p.x.shape[0], ham.C, ham.W
+    assert (B * C) % 2 == 1
+    dev = x.device
+    views = []
+    for shape, dt in (((B, C, W), torch.int64), ((B, C), torch.float64), ((B, C), torch.int8), ((B, C), torch.int32)):
+        buf = torch.empty(int(np.prod(shape)) + 1, dtype=dt, device=dev)
+        views.append(buf[1:].view(shape))
+    assert views[0].data_ptr() % 16 == 8 and views[2].data_ptr() % 2 == 1
+    xp, hv, sg, ex = ham.connect(x, out=tuple(views))
+    torch.cuda.synchronize()
+    oxp, ohv, osg, oex = oracle_connect(p, p.x)
+    assert np.array_equal(words_from_dev(xp), oxp)
+    assert np.array_equal(sg.cpu().numpy(), osg)
+    assert np.array_equal(ex.cpu().numpy().view(np.uint32), oex)
+    assert np.all(np.abs(hv.cpu().numpy() - ohv) <= 1e-13 * np.maximum(1.0, np.abs(ohv)))
+    a = ham.connect(x)   # aligned outputs: the paired path, same values
+    for u, v in zip(a, (xp, hv, sg, ex)):
+        assert torch.equal(u, v)
+
+
 def test_connect_determinism():
     p = synth.make_problem(1, samples=4)
     ham = make_ham(p)
