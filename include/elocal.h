@@ -147,6 +147,9 @@ size_t elocal_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t B, int
  * order). Values: diagonal sum_k h_kk + 1/2 sum_kl [(kk|ll) - (kl|lk)]; single
  * h_ai + sum_k [(ai|kk) - (ak|ki)]; double (ai|bj) - (aj|bi) (spin-orbital integrals).
  * Samples must be in the sector (unchecked here; see elocal_check_samples).
+ * Outputs of any alignment are accepted. With xp and hval aligned to 16 bytes, exc to 8 and
+ * sign to 2 (as fresh allocations are), and C >= 512, the lists are written two entries
+ * per thread with vector stores, which is faster; the contents are the same.
  */
 elocal_status elocal_connect(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B,
                              void* ws, size_t ws_bytes, uint64_t* xp, double* hval,
