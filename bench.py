@@ -78,6 +78,8 @@ def main():
                     help="draws of the batch autoregressive sampler leg (FP64 ansatz of the workload); 0 skips")
     ap.add_argument("--pauli-samples", type=int, default=1024,
                     help="samples of the Pauli-string route leg (Algorithm 1 over unique flips); 0 skips")
+    ap.add_argument("--dedup-reps", type=int, default=5,
+                    help="timed runs of the deduplicated evaluation on the 8-orbital workload; 0 skips")
     ap.add_argument("--kpm-moments", type=int, default=64,
                     help="Chebyshev moments of the KPM leg (12 orbitals, 6a+6b, 853,776 determinants); 0 skips")
     ap.add_argument("--connect-reps", type=int, default=3,
@@ -268,6 +270,40 @@ def main():
                               "build_s": t_build, "kernel_ms": pms, "slater_condon_kernel_ms": sms,
                               "ansatz_rows_ratio": (n_flip - 1) / (C - 1), "time_ratio": pms / sms,
                               "max_rel_diff_vs_slater_condon": diff}
+
+    # --- deduplicated evaluation (each distinct x' of the batch once) against the fused kernel,
+    # on the 8-orbital workload (1024 samples x 361 listed pairs); whole calls between events
+    if args.dedup_reps > 0:
+        dp = synth.make_problem(0)
+        dsys = dp.system
+        dham = elocal.Hamiltonian(dp.h1e, dp.eri, dsys.n, dsys.n_alpha, dsys.n_beta)
+        dth = torch.tensor(dp.theta).to(dev).float().to(torch.bfloat16).contiguous()
+        dans = elocal.Ansatz(dsys.widths, dth, elocal.BF16)
+        dx = torch.from_numpy(dp.x.view(np.int64).copy()).to(dev)
+        ed = torch.empty((dx.shape[0], 2), dtype=torch.float64, device=dev)
+        ef = torch.empty((dx.shape[0], 2), dtype=torch.float64, device=dev)
+        _, _, cnt = dham.eval_dedup(dans, dx, out=ed)
+        dham.eval(dans, dx, out=ef, want_logpsi=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.dedup_reps):
+            dham.eval_dedup(dans, dx, out=ed)
+        e1.record()
+        torch.cuda.synchronize()
+        dms = e0.elapsed_time(e1) / args.dedup_reps
+        e0.record()
+        for _ in range(args.dedup_reps):
+            dham.eval(dans, dx, out=ef, want_logpsi=False)
+        e1.record()
+        torch.cuda.synchronize()
+        fms = e0.elapsed_time(e1) / args.dedup_reps
+        out["dedup"] = {"workload": "8 orbitals, 4a+4b, 1024 samples, 361 listed per sample",
+                        "listed": int(dx.shape[0]) * dham.C, "distinct": int(cnt.item()),
+                        "ms": dms, "fused_ms": fms,
+                        "max_abs_diff_vs_fused": float((ed - ef).abs().max().item()),
+                        "note": "whole calls on the caller's stream, HIP events around them"}
+        del dham, dans
 
     # --- KPM: Chebyshev moments on a full-sector vector (12 orbitals, 6a+6b); each step is
     # one sector-wide H v (row-by-row generator + Slater--Condon + ranked gathers)
