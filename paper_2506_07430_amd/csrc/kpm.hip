@@ -62,7 +62,8 @@ struct KpmSingle {
 // y = ch (H v) + cv v + cz z over the whole sector (z may be null); per wave, the
 // partial sums of y.y and y.v over its rows (fixed row order) go to partial[wave].
 // LDS per wave (stride `wstride` bytes): the row's SampleCtx, its nSa + nSb
-// single-excitation values, then its table of single excitations. Singles and
+// single-excitation values, then its table of single excitations; after the four wave
+// areas, rows 0..n-1 of the binomial table. Singles and
 // opposite-spin doubles (an alpha single u1 with a beta single u2) come from the table:
 // x' has rank (ra + drank(u1)) C(n, n_beta) + rb + drank(u2), and applying a_I, a_J, a+_B,
 // a+_A in that order has parity par(u1) + par(u2) + [I < J] + [I < B] + [J < A] + [B < A]
@@ -85,12 +86,17 @@ __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* 
        (KpmSingle*)(smem + wid * wstride + sizeof(SampleCtx) + 8u * nS)};
   const uint32_t ab0 = 1u + nS + S.nDaa + S.nDbb;   // first opposite-spin double
   const int n = S.n;
+  // rows 0..n-1 of the binomial table in LDS (after the four wave areas): the rankings read
+  // it inside data-dependent loops, where every global load would be waited for in turn
+  uint32_t* sbin = (uint32_t*)(smem + 4u * wstride);
+  for (uint32_t i = threadIdx.x; i < (uint32_t)n * 65u; i += blockDim.x) sbin[i] = binom[i];
+  __syncthreads();
   const int64_t wave = (int64_t)blockIdx.x * 4 + wid, nwaves = (int64_t)gridDim.x * 4;
   double yy = 0.0, yv = 0.0;
   for (int64_t r = wave; r < dim; r += nwaves) {
     const uint32_t ra = (uint32_t)(r / nb_dim), rb = (uint32_t)(r % nb_dim);
     uint64_t x[NW];
-    sector_unrank<NW>(binom, S.n, S.na, S.nb, ra, rb, x);
+    sector_unrank<NW>(sbin, S.n, S.na, S.nb, ra, rb, x);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -111,7 +117,7 @@ __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* 
       flip<NW>(y1, I);
       par ^= parity_below<NW>(y1, A);
       flip<NW>(y1, A);
-      wc.T[u].drank = (int32_t)spin_rank<NW>(binom, y1, spin) - (int32_t)(spin ? rb : ra);
+      wc.T[u].drank = (int32_t)spin_rank<NW>(sbin, y1, spin) - (int32_t)(spin ? rb : ra);
       wc.T[u].info = (uint32_t)I | ((uint32_t)A << 8) | ((uint32_t)par << 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -146,8 +152,8 @@ __global__ void __launch_bounds__(256) k_sector_apply(SysDev S, const uint32_t* 
           uint64_t xo[NW];
           neg = apply_excitation<NW>(x, e, xo) < 0;
           val = excitation_value(S, e, wc.F, ed);
-          idx = e.spin == 0 ? (int64_t)spin_rank<NW>(binom, xo, 0) * nb_dim + rb
-                            : (int64_t)ra * nb_dim + spin_rank<NW>(binom, xo, 1);
+          idx = e.spin == 0 ? (int64_t)spin_rank<NW>(sbin, xo, 0) * nb_dim + rb
+                            : (int64_t)ra * nb_dim + spin_rank<NW>(sbin, xo, 1);
         }
         acc += (neg ? -val : val) * v[idx];
       }
@@ -283,7 +289,7 @@ hipError_t launch_sector_apply(const SysDev& S, const uint32_t* binom, int64_t d
   const uint32_t nS = S.nSa + S.nSb;
   // per wave: SampleCtx, nS single values (8 B), nS table rows (8 B)
   const uint32_t wstride = (uint32_t)((sizeof(SampleCtx) + 16u * (nS ? nS : 1u) + 15u) & ~15u);
-  const size_t lds = 4u * wstride;
+  const size_t lds = 4u * wstride + (size_t)S.n * 65u * sizeof(uint32_t);   // + binomial rows
   if (lds > 65536) {
     auto kern = (S.W == 1) ? (const void*)k_sector_apply<1> : (const void*)k_sector_apply<2>;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
