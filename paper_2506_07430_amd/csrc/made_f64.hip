@@ -131,13 +131,14 @@ __device__ __forceinline__ void kloop_f64_whole(const double* __restrict__ wp, i
   }
 }
 
-// Network on one 16-row block (row r of lane r); epi(ob, acc) per output block.
-// W: packed weights (layer l at fragment woff[l]); WL: the output layer's fragment 0,
-// which may be a copy in LDS.
+// Network on one 16-row block (row r of lane r); epi(ob, acc) per output block ob in
+// [ob_lo, ob_hi) (all of them by default). W: packed weights (layer l at fragment woff[l]);
+// WL: the output layer's fragment 0, which may be a copy in LDS.
 template <int HMAX, int NW, class Epi>
 __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ W,
                                         const double* __restrict__ WL, const double* __restrict__ bias,
-                                        const uint64_t (&xr)[NW], int lane, Epi&& epi) {
+                                        const uint64_t (&xr)[NW], int lane, Epi&& epi, int ob_lo = 0,
+                                        int ob_hi = kMaxOutBlocks) {
   constexpr int OB = HMAX / 16;
   constexpr int KS = HMAX / 4;
   constexpr int KCH = HMAX >= 256 ? 4 : 8;   // k-steps per weight-load chunk
@@ -187,9 +188,9 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
     for (int ob = 0; ob < OB; ++ob) cur[ob] = nxt[ob];
   }
   {
-    const int l = M.L, nk = M.nk[l], nob = M.nob[l];
+    const int l = M.L, nk = M.nk[l], nob = min(M.nob[l], ob_hi);
 #pragma unroll 1
-    for (int ob = 0; ob < nob; ++ob) {
+    for (int ob = ob_lo; ob < nob; ++ob) {
       const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
       f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
       const double* wp = WL + (size_t)(ob * nk) * 64 + lane;
@@ -441,7 +442,7 @@ __global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, const ui
 #pragma unroll
       for (int q = 0; q < 4; ++q) probs[rb * 4 + q] = ok[q] ? exp(z[q] - lse) : 0.0;
     }
-  });
+  }, k >> 2, (k >> 2) + 1);   // only orbital k's output block
 }
 
 hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta, void* frag,

@@ -38,7 +38,7 @@ __device__ __forceinline__ double bas_uniform(uint32_t j, uint32_t i, uint32_t k
 }
 
 // ----------------------------------------------------------------------------- kernels
-// Draw counts of prefix i (one block per prefix): counts[i][s].
+// Draw counts of prefix i (gridDim.y blocks per prefix): counts[i][s].
 __global__ void __launch_bounds__(256) k_bas_counts(const double* __restrict__ probs, const int64_t* __restrict__ w,
                                                     int k, uint64_t seed, int64_t* __restrict__ counts) {
   __shared__ unsigned long long cnt[4];
@@ -61,7 +61,9 @@ __global__ void __launch_bounds__(256) k_bas_counts(const double* __restrict__ p
   }
   unsigned long long c[4] = {0ull, 0ull, 0ull, 0ull};
   const int64_t wi = w[i];
-  for (int64_t j = threadIdx.x; j < wi; j += blockDim.x) {
+  // draws j of prefix i: this block takes j = y * 256 + thread (mod 256 gridDim.y)
+  const int64_t stride = (int64_t)blockDim.x * gridDim.y;
+  for (int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; j < wi; j += stride) {
     const double u = bas_uniform((uint32_t)j, (uint32_t)i, (uint32_t)k, seed);
     int cat = last;
 #pragma unroll
@@ -73,7 +75,15 @@ __global__ void __launch_bounds__(256) k_bas_counts(const double* __restrict__ p
   for (int s = 0; s < 4; ++s)
     if (c[s]) atomicAdd(&cnt[s], c[s]);
   __syncthreads();
-  if (threadIdx.x < 4) counts[4 * i + threadIdx.x] = (int64_t)cnt[threadIdx.x];
+  if (threadIdx.x < 4) {
+    if (gridDim.y == 1) counts[4 * i + threadIdx.x] = (int64_t)cnt[threadIdx.x];
+    else if (cnt[threadIdx.x]) atomicAdd((unsigned long long*)&counts[4 * i + threadIdx.x], cnt[threadIdx.x]);
+  }
+}
+
+__global__ void k_bas_zero(int64_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // Number of surviving children per prefix, and their exclusive scan (blocks of 1024,
@@ -152,7 +162,12 @@ hipError_t launch_bas_step(const SysDev& S, const MadeDev& M, int hmax, const ui
   if (U <= 0) return hipErrorInvalidValue;
   hipError_t e = launch_bas_probs(S, M, hmax, pre, U, k, probs, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bas_counts, dim3((unsigned)U), dim3(256), 0, st, probs, w, k, seed, counts);
+  // few prefixes (the first orbitals) carry all the draws: their draws are spread over up
+  // to 64 blocks each, whose integer counts are added atomically (order-independent)
+  const unsigned ysplit = U >= 2048 ? 1u : (unsigned)(2048 / U < 64 ? 2048 / U : 64);
+  if (ysplit > 1)
+    hipLaunchKernelGGL(k_bas_zero, dim3((unsigned)((4 * U + 255) / 256)), dim3(256), 0, st, counts, 4 * U);
+  hipLaunchKernelGGL(k_bas_counts, dim3((unsigned)U, ysplit), dim3(256), 0, st, probs, w, k, seed, counts);
   const int64_t nblk = (U + 1023) / 1024;
   hipLaunchKernelGGL(k_bas_scan_blocks, dim3((unsigned)nblk), dim3(1024), 0, st, counts, U, off, btot);
   hipLaunchKernelGGL(k_bas_scan_totals, dim3(1), dim3(1024), 0, st, btot, nblk, total);
