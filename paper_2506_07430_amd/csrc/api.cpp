@@ -1014,7 +1014,8 @@ elocal_status elocal_sample(elocal_t h, elocal_stream s, const elocal_ansatz* a,
   int cur = 0;
   for (int k = 0; k < h->sys.n; ++k) {
     HIP_TRY(launch_bas_step(h->sys, M, G.hmax, w.pre[cur], w.w[cur], U, k, seed, w.probs, w.counts, w.off, w.btot,
-                            w.total, w.pre[1 - cur], w.w[1 - cur], max_unique, st), "sampling step launch");
+                            w.total, w.pre[1 - cur], w.w[1 - cur], max_unique, n_samples, st),
+            "sampling step launch");
     int64_t next = 0;
     HIP_TRY(hipMemcpyAsync(&next, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, st), "count copy");
     HIP_TRY(hipStreamSynchronize(st), "sampling step sync");

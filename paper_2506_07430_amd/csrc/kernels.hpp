@@ -143,12 +143,14 @@ hipError_t launch_dd_assemble(const uint64_t* xp, const double* hval, int64_t B,
 
 // Batch autoregressive sampling: conditional of orbital k for U prefixes (FP64 ansatz),
 // and one full tree step (conditionals, Philox draws, scan, children). `total` receives
-// the number of children (entries beyond `cap` are not written).
+// the number of children (entries beyond `cap` are not written). `ndraws` is the number of
+// draws of the whole tree (every step's weights sum to it).
 hipError_t launch_bas_probs(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, int64_t U, int k,
                             double* probs, hipStream_t st);
 hipError_t launch_bas_step(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* w,
                            int64_t U, int k, uint64_t seed, double* probs, int64_t* counts, int64_t* off,
-                           int64_t* btot, int64_t* total, uint64_t* child, int64_t* cw, int64_t cap, hipStream_t st);
+                           int64_t* btot, int64_t* total, uint64_t* child, int64_t* cw, int64_t cap, int64_t ndraws,
+                           hipStream_t st);
 
 // Statistics and gradient (FP64).
 hipError_t launch_stats(const double* eloc, const double* w, int64_t B, double* stats, hipStream_t st);

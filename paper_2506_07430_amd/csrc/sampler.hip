@@ -86,6 +86,86 @@ __global__ void k_bas_zero(int64_t* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// Exclusive scan of the prefix weights within blocks of 1024 (woff), and the block totals.
+__global__ void __launch_bounds__(1024) k_bas_wscan_blocks(const int64_t* __restrict__ w, int64_t U,
+                                                           int64_t* __restrict__ woff, int64_t* __restrict__ btot) {
+  __shared__ int64_t s[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int64_t v = i < U ? w[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t t = threadIdx.x >= (unsigned)d ? s[threadIdx.x - d] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < U) woff[i] = s[threadIdx.x] - v;
+  if (threadIdx.x == 1023) btot[blockIdx.x] = s[1023];
+}
+
+// Draw counts over the flat draw index: draw j of the step belongs to the prefix i whose
+// weight range [off_i, off_i + w_i) holds j (off: block offsets boff, then woff within the
+// block), and is draw j - off_i of that prefix, so it uses the same uniform as in
+// k_bas_counts. Many prefixes with few draws each then cost one thread per draw instead of
+// one block per prefix. A wave whose draws all fall in one prefix adds its four counts once;
+// otherwise every draw adds 1 (integer atomics: the totals do not depend on their order).
+__global__ void __launch_bounds__(256) k_bas_counts_flat(const double* __restrict__ probs,
+                                                         const int64_t* __restrict__ woff,
+                                                         const int64_t* __restrict__ boff, int64_t nblk, int64_t U,
+                                                         const int64_t* __restrict__ total, int k, uint64_t seed,
+                                                         int64_t* __restrict__ counts) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = *total;
+  const bool live = j < N;
+  int64_t i = 0, jl = 0;
+  int cat = -1;
+  if (live) {
+    // block: the last b with boff[b] <= j (boff ascending, boff[0] = 0)
+    int64_t lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    const int64_t b = lo, r = j - boff[b];
+    int64_t l0 = b * 1024, l1 = (b * 1024 + 1023 < U ? b * 1024 + 1023 : U - 1);
+    while (l0 < l1) {
+      const int64_t mid = (l0 + l1 + 1) >> 1;
+      if (woff[mid] <= r) l0 = mid; else l1 = mid - 1;
+    }
+    i = l0;
+    jl = r - woff[i];
+    const double p0 = probs[4 * i], p1 = probs[4 * i + 1], p2 = probs[4 * i + 2], p3 = probs[4 * i + 3];
+    const double pr[4] = {p0, p1, p2, p3};
+    double run[4];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (pr[q] > 0.0) {
+        acc = acc + pr[q];
+        cat = q;
+      }
+      run[q] = acc;
+    }
+    const double u = bas_uniform((uint32_t)jl, (uint32_t)i, (uint32_t)k, seed);
+#pragma unroll
+    for (int q = 3; q >= 0; --q)
+      if (pr[q] > 0.0 && u < run[q]) cat = q;
+  }
+  const int64_t i0 = __shfl(i, 0);
+  const uint64_t act = __ballot(live && cat >= 0);
+  if (__ballot(live && cat >= 0 && i == i0) == act) {   // one prefix for the whole wave
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t m = __ballot(live && cat == q);
+      if (lane == 0 && m) atomicAdd((unsigned long long*)&counts[4 * i0 + q], (unsigned long long)__popcll(m));
+    }
+  } else if (live && cat >= 0) {
+    atomicAdd((unsigned long long*)&counts[4 * i + cat], 1ull);
+  }
+}
+
 // Number of surviving children per prefix, and their exclusive scan (blocks of 1024,
 // then the block totals, then the block offsets added).
 __global__ void __launch_bounds__(1024) k_bas_scan_blocks(const int64_t* __restrict__ counts, int64_t U,
@@ -158,17 +238,26 @@ __global__ void k_bas_emit(const uint64_t* __restrict__ pre, const int64_t* __re
 // ----------------------------------------------------------------------------- launchers
 hipError_t launch_bas_step(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* w,
                            int64_t U, int k, uint64_t seed, double* probs, int64_t* counts, int64_t* off,
-                           int64_t* btot, int64_t* total, uint64_t* child, int64_t* cw, int64_t cap, hipStream_t st) {
-  if (U <= 0) return hipErrorInvalidValue;
+                           int64_t* btot, int64_t* total, uint64_t* child, int64_t* cw, int64_t cap, int64_t ndraws,
+                           hipStream_t st) {
+  if (U <= 0 || ndraws <= 0) return hipErrorInvalidValue;
   hipError_t e = launch_bas_probs(S, M, hmax, pre, U, k, probs, st);
   if (e != hipSuccess) return e;
   // few prefixes (the first orbitals) carry all the draws: their draws are spread over up
   // to 64 blocks each, whose integer counts are added atomically (order-independent)
   const unsigned ysplit = U >= 2048 ? 1u : (unsigned)(2048 / U < 64 ? 2048 / U : 64);
-  if (ysplit > 1)
-    hipLaunchKernelGGL(k_bas_zero, dim3((unsigned)((4 * U + 255) / 256)), dim3(256), 0, st, counts, 4 * U);
-  hipLaunchKernelGGL(k_bas_counts, dim3((unsigned)U, ysplit), dim3(256), 0, st, probs, w, k, seed, counts);
   const int64_t nblk = (U + 1023) / 1024;
+  hipLaunchKernelGGL(k_bas_zero, dim3((unsigned)((4 * U + 255) / 256)), dim3(256), 0, st, counts, 4 * U);
+  if (U < 2048) {
+    hipLaunchKernelGGL(k_bas_counts, dim3((unsigned)U, ysplit), dim3(256), 0, st, probs, w, k, seed, counts);
+  } else {
+    // many prefixes: one thread per draw over the flat draw index (off, btot and total are
+    // free until the children's scan below)
+    hipLaunchKernelGGL(k_bas_wscan_blocks, dim3((unsigned)nblk), dim3(1024), 0, st, w, U, off, btot);
+    hipLaunchKernelGGL(k_bas_scan_totals, dim3(1), dim3(1024), 0, st, btot, nblk, total);
+    hipLaunchKernelGGL(k_bas_counts_flat, dim3((unsigned)((ndraws + 255) / 256)), dim3(256), 0, st, probs, off, btot,
+                       nblk, U, total, k, seed, counts);
+  }
   hipLaunchKernelGGL(k_bas_scan_blocks, dim3((unsigned)nblk), dim3(1024), 0, st, counts, U, off, btot);
   hipLaunchKernelGGL(k_bas_scan_totals, dim3(1), dim3(1024), 0, st, btot, nblk, total);
   if (S.W == 1)
