@@ -131,23 +131,31 @@ __device__ __forceinline__ void kloop_f64_whole(const double* __restrict__ wp, i
   }
 }
 
+// Hidden blocks to compute per layer (with CAP): the rest are set to zero.
+struct HiddenCaps {
+  int nob[kMaxLayers];
+};
+
 // Network on one 16-row block (row r of lane r); epi(ob, acc) per output block ob in
 // [ob_lo, ob_hi) (all of them by default). W: packed weights (layer l at fragment woff[l]);
-// WL: the output layer's fragment 0, which may be a copy in LDS.
-template <int HMAX, int NW, class Epi>
+// WL: the output layer's fragment 0, which may be a copy in LDS. With CAP only the first
+// caps.nob[l] blocks of hidden layer l are computed and the others are zero (a block the
+// caller needs must not depend on the skipped ones).
+template <int HMAX, int NW, bool CAP = false, class Epi>
 __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ W,
                                         const double* __restrict__ WL, const double* __restrict__ bias,
                                         const uint64_t (&xr)[NW], int lane, Epi&& epi, int ob_lo = 0,
-                                        int ob_hi = kMaxOutBlocks) {
+                                        int ob_hi = kMaxOutBlocks, const HiddenCaps& caps = HiddenCaps{}) {
   constexpr int OB = HMAX / 16;
   constexpr int KS = HMAX / 4;
   constexpr int KCH = HMAX >= 256 ? 4 : 8;   // k-steps per weight-load chunk
   const int g = lane >> 4;
   f64x4 cur[OB];
   {
-    const int nk = M.nk[0], nob = M.nob[0];
+    const int nk = M.nk[0], nob = CAP ? min(M.nob[0], caps.nob[0]) : M.nob[0];
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
+      if (CAP && ob >= nob) cur[ob] = f64x4{0.0, 0.0, 0.0, 0.0};
       if (ob < nob) {
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[0][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[0] + 16 * ob + 4 * g);
@@ -169,10 +177,11 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
     }
   }
   for (int l = 1; l < M.L; ++l) {
-    const int nk = M.nk[l], nob = M.nob[l];
+    const int nk = M.nk[l], nob = CAP ? min(M.nob[l], caps.nob[l]) : M.nob[l];
     f64x4 nxt[OB];
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
+      if (CAP && ob >= nob) nxt[ob] = f64x4{0.0, 0.0, 0.0, 0.0};
       if (ob < nob) {
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
         f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
@@ -408,8 +417,9 @@ __global__ void __launch_bounds__(256)
 // Conditional of orbital k for every prefix: probs[i][s] (0 where s is not reachable).
 // FP64 network, 16 prefixes per wave (the layout of the FP64 sample pass).
 template <int HMAX, int NW>
-__global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, const uint64_t* __restrict__ pre,
-                                                   int64_t U, int k, double* __restrict__ probs) {
+__global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, HiddenCaps caps,
+                                                   const uint64_t* __restrict__ pre, int64_t U, int k,
+                                                   double* __restrict__ probs) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t b0 = wave * 16;
@@ -420,8 +430,8 @@ __global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, const ui
   uint64_t xr[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) xr[w] = pre[bb * NW + w];
-  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.wfrag + (size_t)M.woff[M.L] * 64,
-                    (const double*)M.bias, xr, lane, [&](int ob, const f64x4& z) {
+  mlp_f64<HMAX, NW, true>(M, (const double*)M.wfrag, (const double*)M.wfrag + (size_t)M.woff[M.L] * 64,
+                          (const double*)M.bias, xr, lane, [&](int ob, const f64x4& z) {
     if (4 * ob + g != k) return;
     const int cu = count_spin_below<NW>(xr, k, 0), cd = count_spin_below<NW>(xr, k, 1);
     const int left = n - k - 1;
@@ -442,7 +452,7 @@ __global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, const ui
 #pragma unroll
       for (int q = 0; q < 4; ++q) probs[rb * 4 + q] = ok[q] ? exp(z[q] - lse) : 0.0;
     }
-  }, k >> 2, (k >> 2) + 1);   // only orbital k's output block
+  }, k >> 2, (k >> 2) + 1, caps);   // only orbital k's output block and what it depends on
 }
 
 hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta, void* frag,
@@ -538,8 +548,18 @@ static hipError_t bas_probs_h(const SysDev& S, const MadeDev& M, const uint64_t*
                               hipStream_t st) {
   const int64_t waves = (U + 15) / 16;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
-  if (S.W == 1) hipLaunchKernelGGL((k_bas_probs<HMAX, 1>), dim3(blocks), dim3(256), 0, st, S, M, pre, U, k, probs);
-  else hipLaunchKernelGGL((k_bas_probs<HMAX, 2>), dim3(blocks), dim3(256), 0, st, S, M, pre, U, k, probs);
+  // orbital k's logits see the last hidden layer's units of degree <= k, and a hidden unit
+  // of degree d only units of degree <= d below it: in every hidden layer the units of
+  // degree <= k, the first ones of the degree-sorted packing
+  HiddenCaps caps{};
+  for (int l = 0; l < M.L; ++l) {
+    const int w = M.nout[l], q = S.n - 1;
+    int cnt = 0;
+    for (int r = 0; r < q && r < k; ++r) cnt += (w > r) ? (w - r - 1) / q + 1 : 0;   // degree r + 1 <= k
+    caps.nob[l] = (cnt + 15) / 16;
+  }
+  if (S.W == 1) hipLaunchKernelGGL((k_bas_probs<HMAX, 1>), dim3(blocks), dim3(256), 0, st, S, M, caps, pre, U, k, probs);
+  else hipLaunchKernelGGL((k_bas_probs<HMAX, 2>), dim3(blocks), dim3(256), 0, st, S, M, caps, pre, U, k, probs);
   return hipGetLastError();
 }
 
