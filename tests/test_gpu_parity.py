@@ -349,8 +349,9 @@ def test_bad_arguments_raise():
     p = synth.make_problem(0)
     ham = make_ham(p)
     th_dev, _ = theta_for(p.theta, elocal.FP64)
+    # width not a multiple of 32: the descriptor is accepted, the library rejects the shape
+    bad = elocal.Ansatz((48,), th_dev, elocal.FP64)
     with pytest.raises(elocal.ElocalError):
-        elocal.Ansatz((48,), th_dev, elocal.FP64).ref()  # width not multiple of 32
-        ham.eval(elocal.Ansatz((48,), th_dev, elocal.FP64), words_to_dev(p.x[:4]))
+        ham.eval(bad, words_to_dev(p.x[:4]))
     with pytest.raises(elocal.ElocalError):
         ham.eval(elocal.Ansatz((32,), th_dev.float().to(torch.bfloat16), elocal.FP64), words_to_dev(p.x[:4]))

@@ -365,6 +365,46 @@ def test_gradient_matches_finite_difference_of_rayleigh_quotient():
         assert abs(fd - g[i]) < 1e-7 + 1e-6 * abs(fd), (i, fd, g[i])
 
 
+# ----------------------------------------------------------------------------- energy statistics
+def test_energy_stats_constant_local_energy():
+    """Methods, batch estimator: a constant local energy c is its own mean, with variance 0,
+    whatever the weights."""
+    w = np.array([1.0, 7.0, 2.5, 1e-3, 40.0])
+    c = -12.375 + 0.625j
+    e_re, e_im, var, sw = energy.energy_stats(np.full(w.size, c), w)
+    assert (e_re, e_im) == (c.real, c.imag)
+    assert var == 0.0
+    assert sw == w.sum()
+
+
+def test_energy_stats_multiplicities_equal_repeated_rows():
+    """Unique samples with integer multiplicities w_i give the plain average over the
+    batch in which sample i appears w_i times (all weights 1)."""
+    g = np.random.default_rng(17)
+    el = g.normal(-30.0, 2.0, 9) + 1j * g.normal(0.0, 0.3, 9)
+    w = np.array([1, 4, 2, 9, 1, 3, 6, 2, 5], dtype=np.float64)
+    expanded = np.repeat(el, w.astype(int))
+    got = energy.energy_stats(el, w)
+    mean = expanded.mean()
+    var = np.mean(np.abs(expanded - mean) ** 2)
+    want = (mean.real, mean.imag, var, float(expanded.size))
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-12)
+    # and the same as the repeated list passed with unit weights
+    assert np.allclose(got, energy.energy_stats(expanded, np.ones(expanded.size)), rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("w1,w2", [(1.0, 1.0), (3.0, 1.0), (0.25, 5.0)])
+def test_energy_stats_two_point_closed_form(w1, w2):
+    """Two local energies a, b with weights w1, w2: mean (w1 a + w2 b) / (w1 + w2) and
+    variance w1 w2 |a - b|^2 / (w1 + w2)^2 (the weighted, not the sample, variance)."""
+    a, b = -7.0 + 1.0j, -3.0 - 2.0j
+    e_re, e_im, var, sw = energy.energy_stats(np.array([a, b]), np.array([w1, w2]))
+    mean = (w1 * a + w2 * b) / (w1 + w2)
+    assert abs(complex(e_re, e_im) - mean) < 1e-14
+    assert abs(var - w1 * w2 * abs(a - b) ** 2 / (w1 + w2) ** 2) < 1e-13
+    assert sw == w1 + w2
+
+
 # ----------------------------------------------------------------------------- bf16 / sampler
 def test_bf16_rounding_matches_torch():
     import torch
