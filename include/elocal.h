@@ -65,17 +65,22 @@ typedef enum {
   ELOCAL_E_UNSUPPORTED = 6  /* shape outside what the kernels handle                     */
 } elocal_status;
 
-/* Arithmetic of the ansatz. H_{xx'}, ratios and every sum stay FP64 in both modes. */
+/* Arithmetic of the ansatz. H_{xx'}, ratios and every sum stay FP64 in every mode. */
 enum {
   ELOCAL_FP64 = 0,   /* theta is double; ansatz on FP64 matrix cores                     */
-  ELOCAL_BF16 = 1,   /* theta is bfloat16 (uint16 bit patterns); ansatz GEMMs on BF16
-                        matrix cores with FP32 accumulation, each hidden activation
-                        carried as a hi+lo pair of bfloat16 values (<= 2^-16 relative)    */
-  ELOCAL_BF16X3 = 2  /* as ELOCAL_BF16 with three bfloat16 terms per activation
-                        (<= 2^-24 relative; 1.5x the matrix-core work after the first
-                        layer). The rounding of the two-term split, summed over a very
-                        long connected list, grows past 1e-5 Ha per local energy around
-                        n = 60 (1.1e6 connected determinants); three terms keep it below */
+  ELOCAL_BF16 = 1,   /* theta is bfloat16 (uint16 bit patterns); the ansatz products run
+                        on the 16-bit matrix cores with FP32 accumulation: the weights are
+                        used as fp16 (every bfloat16 value in [2^-17, 65504] is an fp16
+                        number; smaller ones move by at most 2^-25), and each hidden
+                        activation is carried as a hi+lo pair of fp16 values (<= 2^-22
+                        relative, 2^-25 absolute for the smallest). Weights and hidden
+                        activations must stay below 65504 in magnitude (fp16 range):
+                        larger ones make the results non-finite. Measured against the FP64
+                        oracle on the same parameters: a few 1e-7 Ha per local energy at
+                        24 orbitals, ~1e-6 Ha at 60 orbitals (1.1e6 connected determinants) */
+  ELOCAL_BF16X3 = 2  /* as ELOCAL_BF16 with three fp16 terms per activation (1.5x the
+                        matrix-core work after the first layer; the FP32 accumulation then
+                        dominates the error, so it is no more accurate in practice)        */
 };
 
 /* Operations, for elocal_workspace_bytes. */

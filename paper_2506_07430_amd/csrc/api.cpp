@@ -105,7 +105,7 @@ struct AnsatzGeom {
   int hmax = 0;
   int precision = 0;   // storage/arithmetic family: ELOCAL_FP64 or ELOCAL_BF16
   int mode = 0;        // the caller's precision (ELOCAL_BF16X3 is in the BF16 family)
-  int nterms = 2;      // bf16 terms per hidden activation (BF16 family)
+  int nterms = 2;      // fp16 terms per hidden activation (BF16 family)
   size_t wbytes = 0, bbytes = 0;
 };
 
@@ -117,8 +117,8 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
   if (!a->widths) return fail(ELOCAL_E_INVALID, "widths is null");
   if (a->precision != ELOCAL_FP64 && a->precision != ELOCAL_BF16 && a->precision != ELOCAL_BF16X3)
     return fail(ELOCAL_E_INVALID, "precision=%d is not ELOCAL_FP64, ELOCAL_BF16 or ELOCAL_BF16X3", a->precision);
-  // BF16 family: bf16 parameters on BF16 matrix cores; the modes differ in the number of
-  // bf16 terms that carry each hidden activation
+  // BF16 family: bf16 parameters on the 16-bit matrix cores; the modes differ in the number of
+  // fp16 terms that carry each hidden activation
   const bool bf = a->precision != ELOCAL_FP64;
   const int L = a->n_hidden;
   int wmax = 0;

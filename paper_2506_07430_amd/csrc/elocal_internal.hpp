@@ -5,7 +5,7 @@
 
 namespace elocal {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -78,7 +78,7 @@ struct MadeDev {
   // needs its first kend[l][ob] k-blocks (the rest of its weights are masked).
   // (32-bit so that a wave-uniform lookup is a scalar load)
   int32_t kend[kMaxLayers][kMaxOutBlocks];
-  const void* wfrag;           // packed weights (bf16x8 per lane or double per lane)
+  const void* wfrag;           // packed weights (8 fp16 per lane or one double per lane)
   const void* bias;            // float (BF16 mode) or double (FP64 mode)
 };
 

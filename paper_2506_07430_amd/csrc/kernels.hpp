@@ -71,7 +71,7 @@ hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_we
                             unsigned grid, hipStream_t st);
 
 // Shape of the BF16 fused kernels (single and multi-system), one block per CU. With two
-// bf16 terms per activation a pass of the network takes one 16-row tile, so that a wave
+// fp16 terms per activation a pass of the network takes one 16-row tile, so that a wave
 // fits in 128 registers up to width 128 (16 waves per block, four per SIMD) and in 256 at
 // width 256 (8 waves, two per SIMD): the VALU and MFMA work of different waves on a SIMD
 // overlap the more waves share it. Three terms take two tiles per pass (8 waves up to
@@ -85,7 +85,7 @@ constexpr int kMaxEvalWavesBF16 = 16;
 // the FP64 suffix sums of its per-orbital log2 probabilities.
 constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(double);
 // Input-expansion table of the fused BF16 kernels, in LDS after the wave contexts: entry v
-// holds the 8 bf16 values (bit j of v ? 1 : 0), the layer-0 operand of 8 input bits.
+// holds the 8 fp16 values (bit j of v ? 1 : 0), the layer-0 operand of 8 input bits.
 constexpr size_t kXLutBytes = 256 * 16;
 // Fused BF16 kernels of at least this width stage only the output layer, followed by
 // layer 0 when it fits too, in LDS (their hidden layers do not fit) and read the rest

@@ -1,5 +1,5 @@
-// Autoregressive ansatz on BF16 matrix cores (v_mfma_f32_16x16x32_bf16) and the fused
-// local-energy kernel built on it.
+// Autoregressive ansatz with bfloat16 parameters on the 16-bit matrix cores
+// (v_mfma_f32_16x16x32_f16) and the fused local-energy kernel built on it.
 //
 // Formulation: every layer is computed transposed, D[unit][row] = W[unit][k] * act[k][row],
 // so the weights are the A operand and the activations of 16 rows the B operand. The
@@ -15,12 +15,15 @@
 // logits of orbital p, hidden units of degree <= p), i.e. a prefix in this order, so
 // o-block ob of layer l multiplies only its first kend[l][ob] k-blocks.
 //
-// Precision: layer-0 inputs are exact 0/1; every later activation a (FP32 after bias
-// and ReLU) is fed as hi = bf16(a) plus lo = bf16(a - hi) (a third term in the
-// three-term mode), one MFMA per term and weight fragment. bf16 keeps 8 significant
-// bits, so two terms represent a to within 2^-16 |a| and three to within 2^-24 |a|.
-// Accumulation is FP32; the ratio exp(dA + i dphi), the matrix element and every sum
-// are FP64.
+// Precision: the caller's weights are bfloat16; the packing stores them as fp16, which
+// holds every bfloat16 value in [2^-17, 65504] exactly (8 significant bits in fp16's 11),
+// so both operand types of the products are fp16 and run at the bfloat16 rate. Layer-0
+// inputs are exact 0/1; every later activation a (FP32 after bias and ReLU) is fed as
+// hi = fp16(a) plus lo = fp16(a - hi) (a third term in the three-term mode), one MFMA
+// per term and weight fragment: two terms represent a to within 2^-22 |a| (fp16 keeps 11
+// significant bits; 2^-25 absolute for the smallest values), where two bfloat16 terms
+// would leave 2^-16 |a|. Accumulation is FP32; the ratio exp(dA + i dphi), the matrix
+// element and every sum are FP64.
 #include <type_traits>
 
 #include "elocal_internal.hpp"
@@ -47,10 +50,20 @@ __device__ __forceinline__ int kslot_bf16(int l, int kb, int g, int j) {
   return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
 }
 
-// Packs the caller's parameters (bf16 bit patterns, natural order) into MFMA A-operand
+// The fp16 pattern of a bf16 value (RNE). Exact for 2^-17 <= |w| <= 65504 (8 significant
+// bits fit fp16's 11, and fp16 subnormals reach down to multiples of 2^-24); smaller values
+// move by at most 2^-25, larger ones overflow to infinity.
+__device__ __forceinline__ unsigned short f16_bits_of_bf16(unsigned short b) {
+  const _Float16 h = (_Float16)__uint_as_float((uint32_t)b << 16);
+  unsigned short r;
+  __builtin_memcpy(&r, &h, 2);
+  return r;
+}
+
+// Packs the caller's parameters (bf16 bit patterns, natural order) into fp16 MFMA A-operand
 // fragments with hidden units in degree order, masked entries zeroed; biases to FP32.
 __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict__ theta,
-                            bf16x8* __restrict__ frag, float* __restrict__ bias) {
+                            h16x8* __restrict__ frag, float* __restrict__ bias) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = M.n, L = M.L;
   if (gid < M.nfrag * 64u) {
@@ -75,9 +88,9 @@ __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict
         if (l == L && o == phase_row_bf16(n)) bits = theta[T.offwphi + k];
         else bits = theta[T.offW[l] + (uint32_t)o * M.nin[l] + k];
       }
-      v[j] = bits;
+      v[j] = f16_bits_of_bf16(bits);
     }
-    bf16x8 out;
+    h16x8 out;
     __builtin_memcpy(&out, v, sizeof(out));
     frag[gid] = out;
   }
@@ -94,48 +107,68 @@ __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict
   }
 }
 
-__device__ __forceinline__ bf16x8 bits_to_bf16x8(uint32_t v) {
+__device__ __forceinline__ h16x8 bits_to_h16x8(uint32_t v) {
   uint32_t w[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
-    w[q] = (((v >> (2 * q)) & 1u) * 0x3F80u) | ((((v >> (2 * q + 1)) & 1u) * 0x3F80u) << 16);
-  bf16x8 r;
+    w[q] = (((v >> (2 * q)) & 1u) * 0x3C00u) | ((((v >> (2 * q + 1)) & 1u) * 0x3C00u) << 16);
+  h16x8 r;
   __builtin_memcpy(&r, w, sizeof(r));
   return r;
 }
 
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 
-// ReLU of a pair, then NT bfloat16 terms whose sum represents each value: t[0] =
-// bf16(a), t[1] = bf16(a - t[0]), t[2] = bf16(a - t[0] - t[1]) (one packed convert per
-// term for both values; the FP32 value of a term is recovered from its bits). Two terms
-// leave at most 2^-16 |a|, three 2^-24 |a|.
+// ReLU of a pair, then NT fp16 terms whose sum represents each value: t[0] = fp16(a),
+// t[1] = fp16(a - t[0]), t[2] = fp16(a - t[0] - t[1]) (one packed convert for the first
+// term of both values; each later term is one fused multiply-add with an fp16 operand
+// that rounds straight to fp16, a - t[0] being exact in FP32). Two terms leave at most
+// 2^-22 |a| for |a| >= 2^-3 and 2^-25 in absolute terms below (fp16 subnormals), three
+// terms far less. Values must stay below 65504 (the fp16 range).
 template <int NT>
 __device__ __forceinline__ void split_pair(float u, float v, uint32_t (&t)[NT]) {
   u = __int_as_float(max(__float_as_int(u), 0));     // ReLU: negative floats are negative ints
   v = __int_as_float(max(__float_as_int(v), 0));
-#pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    bf16x2 h;
-    h[0] = (__bf16)u;
-    h[1] = (__bf16)v;
-    uint32_t hb;
-    __builtin_memcpy(&hb, &h, 4);
-    // opaque to the optimiser: without this it recomputes bf16(u) by a second convert
-    // instead of taking it from hb
-    asm volatile("" : "+v"(hb));
-    t[i] = hb;
-    if (i + 1 < NT) {
-      u -= __uint_as_float(hb << 16);
-      v -= __uint_as_float(hb & 0xFFFF0000u);
+  // a 1.0 the optimiser cannot fold: fma(-t, one, a) then stays one mixed-precision FMA
+  float one;
+  asm("s_mov_b32 %0, 1.0" : "=s"(one));
+  h16x2 h;
+  h[0] = (_Float16)u;
+  h[1] = (_Float16)v;
+  uint32_t hb;
+  __builtin_memcpy(&hb, &h, 4);
+  // opaque to the optimiser: the residuals below read the packed value, not a second convert
+  asm volatile("" : "+v"(hb));
+  t[0] = hb;
+  if (NT > 1) {
+    h16x2 hh;
+    __builtin_memcpy(&hh, &hb, 4);
+    const float ru = __builtin_fmaf(-(float)hh[0], one, u);
+    const float rv = __builtin_fmaf(-(float)hh[1], one, v);
+    h16x2 l;
+    l[0] = (_Float16)ru;
+    l[1] = (_Float16)rv;
+    uint32_t lb;
+    __builtin_memcpy(&lb, &l, 4);
+    t[1] = lb;
+    if (NT > 2) {
+      asm volatile("" : "+v"(lb));
+      h16x2 ll;
+      __builtin_memcpy(&ll, &lb, 4);
+      const float su = __builtin_fmaf(-(float)ll[0], one, ru);
+      const float sv = __builtin_fmaf(-(float)ll[1], one, rv);
+      h16x2 m;
+      m[0] = (_Float16)su;
+      m[1] = (_Float16)sv;
+      __builtin_memcpy(&t[NT > 2 ? 2 : 0], &m, 4);
     }
   }
 }
 
 // Units 4g..4g+3 of block a and of block a+1 -> the 8 k-slots of the next layer, as NT
-// bf16 terms.
+// fp16 terms.
 template <int NT>
-__device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, bf16x8 (&out)[NT]) {
+__device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, h16x8 (&out)[NT]) {
   uint32_t t[4][NT];
   split_pair<NT>(a[0], a[1], t[0]);
   split_pair<NT>(a[2], a[3], t[1]);
@@ -150,8 +183,8 @@ __device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, bf16x
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ f32x4 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma_f16(const h16x8& a, const h16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
@@ -169,9 +202,9 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
 // whose hidden layers do not fit) the output layer is in LDS, followed by layer 0 when it
 // fits too (then read through a generic pointer), and the hidden layers in global memory.
 struct WeightsBF16 {
-  const bf16x8* hid;
-  const bf16x8* l0;
-  const bf16x8* out;
+  const h16x8* hid;
+  const h16x8* l0;
+  const h16x8* out;
 };
 
 // Partial staging (layer 0 and the output layer only) for the widest networks.
@@ -179,15 +212,15 @@ template <int HMAX>
 constexpr bool lds_partial_bf16() { return HMAX >= kLdsPartialWidth; }
 
 __device__ __forceinline__ WeightsBF16 weights_global(const MadeDev& M) {
-  const bf16x8* W = (const bf16x8*)M.wfrag;
+  const h16x8* W = (const h16x8*)M.wfrag;
   return {W, W, W + (size_t)M.woff[M.L] * 64};
 }
 
 template <int HMAX>
 __device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsigned char* smem, uint32_t l0) {
-  const bf16x8* S = (const bf16x8*)smem;
+  const h16x8* S = (const h16x8*)smem;
   if (lds_partial_bf16<HMAX>()) {
-    const bf16x8* G = (const bf16x8*)M.wfrag;
+    const h16x8* G = (const h16x8*)M.wfrag;
     return {G, l0 ? S + (size_t)(M.nfrag - M.woff[M.L]) * 64 : G, S};
   }
   return {S, S, S + (size_t)M.woff[M.L] * 64};
@@ -195,22 +228,22 @@ __device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsig
 
 // Output block ob of the last layer for the NC 16-row tiles (tile c: row r of lane r).
 template <int KB, int NT, int NC>
-__device__ __forceinline__ void out_block(const MadeDev& M, const bf16x8* __restrict__ WL,
-                                          const float* __restrict__ bias, const bf16x8 (&act)[NT][NC][KB],
+__device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restrict__ WL,
+                                          const float* __restrict__ bias, const h16x8 (&act)[NT][NC][KB],
                                           int ob, int lane, f32x4 (&a)[NC]) {
   const int l = M.L, nk = M.nk[l], ke = sgpr(M.kend[l][ob]);
   const f32x4 b4 = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
 #pragma unroll
   for (int c = 0; c < NC; ++c) a[c] = b4;
-  const bf16x8* wp = WL + (size_t)(ob * nk) * 64 + lane;
+  const h16x8* wp = WL + (size_t)(ob * nk) * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     if (kb == 0 || kb < ke) {
-      const bf16x8 w = wp[kb * 64];
+      const h16x8 w = wp[kb * 64];
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int i = 0; i < NT; ++i) a[c] = mfma_bf16(w, act[i][c][kb], a[c]);
+        for (int i = 0; i < NT; ++i) a[c] = mfma_f16(w, act[i][c][kb], a[c]);
     }
   }
 }
@@ -225,20 +258,20 @@ template <int HMAX, int NW, int NT, int NC, bool XLUT = false, class Epi>
 __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt,
                                          const float* __restrict__ bias,
                                          const uint64_t (&xr)[NC][NW], int lane, int ob_first,
-                                         const bf16x8* xlut, Epi&& epi) {
+                                         const h16x8* xlut, Epi&& epi) {
   constexpr int KB = HMAX / 32;
   const int g = lane >> 4;
-  bf16x8 act[NT][NC][KB];
+  h16x8 act[NT][NC][KB];
   // ---- layer 0: exact 0/1 inputs, one MFMA per fragment
   {
     const int nk = M.nk[0], nob = M.nob[0];
-    bf16x8 xin[NC][4];
+    h16x8 xin[NC][4];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
         if (XLUT) xin[c][kb] = xlut[kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u];
-        else xin[c][kb] = bits_to_bf16x8(kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
+        else xin[c][kb] = bits_to_h16x8(kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
@@ -250,24 +283,24 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        const bf16x8* w0p = Wt.l0 + (size_t)((2 * kbo) * nk) * 64 + lane;
-        const bf16x8* w1p = w0p + (size_t)nk * 64;
+        const h16x8* w0p = Wt.l0 + (size_t)((2 * kbo) * nk) * 64 + lane;
+        const h16x8* w1p = w0p + (size_t)nk * 64;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
           if (kb == 0 || kb < ke1) {
-            const bf16x8 w1 = w1p[kb * 64];
+            const h16x8 w1 = w1p[kb * 64];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a1[c] = mfma_bf16(w1, xin[c][kb], a1[c]);
+            for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(w1, xin[c][kb], a1[c]);
             if (kb == 0 || kb < ke0) {
-              const bf16x8 w0 = w0p[kb * 64];
+              const h16x8 w0 = w0p[kb * 64];
 #pragma unroll
-              for (int c = 0; c < NC; ++c) a0[c] = mfma_bf16(w0, xin[c][kb], a0[c]);
+              for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
             }
           }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          bf16x8 t[NT];
+          h16x8 t[NT];
           split_relu<NT>(a0[c], a1[c], t);
 #pragma unroll
           for (int i = 0; i < NT; ++i) act[i][c][kbo] = t[i];
@@ -278,7 +311,7 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
   // ---- hidden layers 1..L-1
   for (int l = 1; l < M.L; ++l) {
     const int nk = M.nk[l], nob = M.nob[l];
-    bf16x8 nxt[NT][NC][KB];
+    h16x8 nxt[NT][NC][KB];
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
@@ -290,14 +323,14 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        const bf16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
-        const bf16x8* w1p = w0p + (size_t)nk * 64;
+        const h16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
+        const h16x8* w1p = w0p + (size_t)nk * 64;
         if constexpr (lds_partial_bf16<HMAX>() && NT == 2) {
           // hidden weights from global memory (few waves per SIMD): a pair's loads are issued
           // in chunks of CH k-blocks, one chunk ahead of the products (the three-term mode has
           // no registers left for this)
           constexpr int CH = 4, NCH = KB / CH;
-          bf16x8 w0b[NCH][CH], w1b[NCH][CH];
+          h16x8 w0b[NCH][CH], w1b[NCH][CH];
 #pragma unroll
           for (int c = 0; c < 1 && c < NCH; ++c)   // prologue: chunk 0
 #pragma unroll
@@ -325,12 +358,12 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
                   for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
-                    for (int i = 0; i < NT; ++i) a1[cc] = mfma_bf16(w1b[c][j], act[i][cc][kb], a1[cc]);
+                    for (int i = 0; i < NT; ++i) a1[cc] = mfma_f16(w1b[c][j], act[i][cc][kb], a1[cc]);
                   if (kb == 0 || kb < ke0) {
 #pragma unroll
                     for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
-                      for (int i = 0; i < NT; ++i) a0[cc] = mfma_bf16(w0b[c][j], act[i][cc][kb], a0[cc]);
+                      for (int i = 0; i < NT; ++i) a0[cc] = mfma_f16(w0b[c][j], act[i][cc][kb], a0[cc]);
                   }
                 }
               }
@@ -340,24 +373,24 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           if (kb == 0 || kb < ke1) {
-            const bf16x8 w1 = w1p[kb * 64];
+            const h16x8 w1 = w1p[kb * 64];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
-              for (int i = 0; i < NT; ++i) a1[c] = mfma_bf16(w1, act[i][c][kb], a1[c]);
+              for (int i = 0; i < NT; ++i) a1[c] = mfma_f16(w1, act[i][c][kb], a1[c]);
             if (kb == 0 || kb < ke0) {
-              const bf16x8 w0 = w0p[kb * 64];
+              const h16x8 w0 = w0p[kb * 64];
 #pragma unroll
               for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int i = 0; i < NT; ++i) a0[c] = mfma_bf16(w0, act[i][c][kb], a0[c]);
+                for (int i = 0; i < NT; ++i) a0[c] = mfma_f16(w0, act[i][c][kb], a0[c]);
             }
           }
         }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          bf16x8 t[NT];
+          h16x8 t[NT];
           split_relu<NT>(a0[c], a1[c], t);
 #pragma unroll
           for (int i = 0; i < NT; ++i) nxt[i][c][kbo] = t[i];
@@ -609,7 +642,7 @@ __device__ __attribute__((noinline)) double2 ratio_term(double hv, float zp, dou
 // order) goes to P.partial[item].
 template <int HMAX, int NW, int NT, class Gen = ScGen>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsBF16& Wt,
-                                               const float* __restrict__ bias, const bf16x8* xlut,
+                                               const float* __restrict__ bias, const h16x8* xlut,
                                                WaveCtxBF16& wc, int64_t item, SampleState<NW>& st, int lane) {
   constexpr int NC = eval_cols_bf16(HMAX, NT);
   const MadeDev& M = P.made;
@@ -745,11 +778,11 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
 template <bool PARTIAL>
 __device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* smem, uint32_t bias_off,
                                               uint32_t l0) {
-  bf16x8* sw = (bf16x8*)smem;
-  const bf16x8* gw = (const bf16x8*)M.wfrag;
+  h16x8* sw = (h16x8*)smem;
+  const h16x8* gw = (const h16x8*)M.wfrag;
   if (PARTIAL) {
     const uint32_t n0 = l0 ? M.woff[1] * 64u : 0u, nl = (M.nfrag - M.woff[M.L]) * 64u;
-    const bf16x8* gl = gw + (size_t)M.woff[M.L] * 64;
+    const h16x8* gl = gw + (size_t)M.woff[M.L] * 64;
     for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) sw[i] = gl[i];
     for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) sw[nl + i] = gw[i];
   } else {
@@ -762,10 +795,10 @@ __device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* s
 
 // Fills the input-expansion table (every thread of the block takes part; the caller
 // synchronises the block before the table is read).
-__device__ __forceinline__ bf16x8* fill_xlut(unsigned char* smem, uint32_t ctx_off) {
+__device__ __forceinline__ h16x8* fill_xlut(unsigned char* smem, uint32_t ctx_off) {
   static_assert((kMaxEvalWavesBF16 * kWaveCtxBytesBF16) % 16 == 0, "input table alignment");
-  bf16x8* lut = (bf16x8*)(smem + ctx_off + kMaxEvalWavesBF16 * kWaveCtxBytesBF16);
-  for (uint32_t v = threadIdx.x; v < 256u; v += blockDim.x) lut[v] = bits_to_bf16x8(v);
+  h16x8* lut = (h16x8*)(smem + ctx_off + kMaxEvalWavesBF16 * kWaveCtxBytesBF16);
+  for (uint32_t v = threadIdx.x; v < 256u; v += blockDim.x) lut[v] = bits_to_h16x8(v);
   return lut;
 }
 
@@ -779,7 +812,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   WeightsBF16 Wt = weights_global(P.made);
   const float* bias = (const float*)P.made.bias;
-  const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
+  const h16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
     stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off, P.lds_l0);
     Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
@@ -803,7 +836,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   WeightsBF16 Wt = weights_global(P.made);
   const float* bias = (const float*)P.made.bias;
-  const bf16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
+  const h16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
   if (LDSW) {
     stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off, P.lds_l0);
     Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
@@ -837,7 +870,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
   int cur = -1;
   WeightsBF16 Wt = {nullptr, nullptr, nullptr};
   const float* bias = nullptr;
-  const bf16x8* xlut = fill_xlut(smem, lds_ctx_off);
+  const h16x8* xlut = fill_xlut(smem, lds_ctx_off);
   __syncthreads();
   const int64_t chunks = first[n_sys];
   for (int64_t chunk = blockIdx.x; chunk < chunks; chunk += gridDim.x) {
@@ -872,7 +905,7 @@ hipError_t launch_pack_bf16(const MadeDev& M, const ThetaLayout& T, const uint16
                             void* frag, float* bias, hipStream_t st) {
   const uint32_t total = M.nfrag * 64u > M.nbias ? M.nfrag * 64u : M.nbias;
   hipLaunchKernelGGL(k_pack_bf16, dim3((total + 255) / 256), dim3(256), 0, st, M, T, theta,
-                     (bf16x8*)frag, bias);
+                     (h16x8*)frag, bias);
   return hipGetLastError();
 }
 

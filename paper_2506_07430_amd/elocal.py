@@ -18,8 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libelocal.so")
 
 FP64 = 0
-BF16 = 1      # two bf16 terms per hidden activation
-BF16X3 = 2    # three bf16 terms per hidden activation
+BF16 = 1      # bfloat16 parameters; two fp16 terms per hidden activation
+BF16X3 = 2    # bfloat16 parameters; three fp16 terms per hidden activation
 OP_CONNECT, OP_EVAL, OP_GRAD = 0, 1, 2
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_CONFIG", 3: "E_WORKSPACE", 4: "E_NOMEM", 5: "E_DEVICE",
