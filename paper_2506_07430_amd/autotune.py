@@ -70,3 +70,34 @@ def tune_eval(ham: elocal.Hamiltonian, ansatz: elocal.Ansatz, x: torch.Tensor,
     best = min(table, key=lambda r: r["ms"])
     ham.tune(best["grid"], best["groups"])
     return table
+
+
+def tune_multi(mev: elocal.MultiEval, hams: Sequence[elocal.Hamiltonian], ansatze: Sequence[elocal.Ansatz],
+               xs: Sequence[torch.Tensor], shapes: Optional[Sequence] = None, reps: int = 1,
+               budget_s: float = 30.0) -> List[Dict]:
+    """The same search for the several-system launch (elocal_eval_multi): the grid comes
+    from the first handle, the groups per work item from each system's handle, so every
+    candidate is set on all of them. Keeps the fastest; returns the timings."""
+    shapes = list(shapes) if shapes is not None else candidates(ansatze[0].precision,
+                                                                max(max(a.widths) for a in ansatze))
+    table, spent = [], 0.0
+    for grid, groups in shapes:
+        for h in hams:
+            h.tune(grid, groups)
+        mev(hams, ansatze, xs)
+        torch.cuda.synchronize()
+        hams[0].timing(True)
+        hams[0].kernel_time(reset=True)
+        for _ in range(reps):
+            mev(hams, ansatze, xs)
+        ms, n = hams[0].kernel_time(reset=True)
+        hams[0].timing(False)
+        ms /= max(n, 1)
+        table.append({"grid": grid, "groups": groups, "ms": ms})
+        spent += ms * (reps + 1) / 1e3
+        if spent > budget_s:
+            break
+    best = min(table, key=lambda r: r["ms"])
+    for h in hams:
+        h.tune(best["grid"], best["groups"])
+    return table

@@ -466,20 +466,34 @@ class ElocEnergy(torch.autograd.Function):
     Backward: grad_output times the VMC gradient 2 Re <(E_loc - <E>) d log Psi*> --
     the variational-energy gradient estimator, not the derivative of the
     fixed-sample mean (the samples themselves depend on theta).
+
+    ``theta`` holds the parameters in the caller's (master) precision: float64 or
+    float32 for a master copy, or bfloat16. In the BF16 modes the forward evaluates the
+    ansatz at theta rounded to bfloat16 (FP32 then round-to-nearest-even); the backward
+    returns the library's FP64 gradient in theta's dtype, so a float64 master copy gets
+    it unrounded (a bfloat16 theta gets it rounded to bfloat16).
+
+    Usage: ``E = ElocEnergy.apply(theta, ham, widths, precision, x, w)``.
     """
 
     @staticmethod
     def forward(ctx, theta, ham: Hamiltonian, widths, precision, x, w):
-        ans = Ansatz(widths, theta.detach().contiguous(), precision)
+        th = theta.detach()
+        if precision == FP64:
+            th = th.to(torch.float64)
+        elif th.dtype != torch.bfloat16:
+            th = th.to(torch.float32).to(torch.bfloat16)
+        ans = Ansatz(widths, th.contiguous(), precision)
         eloc, _ = ham.eval(ans, x, want_logpsi=False)
         st = stats(eloc, w)
         ctx.ham, ctx.ans = ham, ans
         ctx.save_for_backward(x, w, eloc)
         ctx.stats = st
+        ctx.theta_dtype = theta.dtype
         return st[0].clone()
 
     @staticmethod
     def backward(ctx, g):
         x, w, eloc = ctx.saved_tensors
         _, dtheta = ctx.ham.grad(ctx.ans, x, w, eloc)
-        return (g * dtheta).to(ctx.ans.theta.dtype), None, None, None, None, None
+        return (g.to(torch.float64) * dtheta).to(ctx.theta_dtype), None, None, None, None, None

@@ -356,3 +356,12 @@ def test_bad_arguments_raise():
         ham.eval(bad, words_to_dev(p.x[:4]))
     with pytest.raises(elocal.ElocalError):
         ham.eval(elocal.Ansatz((32,), th_dev.float().to(torch.bfloat16), elocal.FP64), words_to_dev(p.x[:4]))
+
+
+def test_grad_n60_full_batch_fd_and_oracle():
+    """60 orbitals (26, 26), 3 x 256 hidden, 1024 samples, BF16 ansatz (the largest
+    workload: forward plus gradient): the library gradient equals the FP64 oracle gradient
+    and central differences on 32 parameters."""
+    p = synth.make_problem(4)
+    assert p.x.shape[0] == 1024
+    _fd_check(p, p.x, p.w, elocal.BF16, 32)
