@@ -185,6 +185,23 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
       }
     }
   }
+  if (bf) {
+    // compact BF16 packing: only the k-blocks each o-block uses
+    uint32_t f = 0;
+    for (int l = 0; l <= L; ++l) {
+      for (int ob = 0; ob <= kMaxOutBlocks; ++ob) M.foff[l][ob] = 0;
+      for (int ob = 0; ob < M.nob[l]; ++ob) {
+        M.foff[l][ob] = (int32_t)f;
+        f += (uint32_t)M.kend[l][ob];
+      }
+      M.foff[l][M.nob[l]] = (int32_t)f;
+      M.woff[l] = (uint32_t)M.foff[l][0];
+    }
+    for (int l = L + 1; l < kMaxLayers; ++l)
+      for (int ob = 0; ob <= kMaxOutBlocks; ++ob) M.foff[l][ob] = (int32_t)f;
+    M.nfrag = f;
+    wo = f;
+  }
   G.wbytes = (size_t)wo * 64 * (bf ? 16 : 8);
   G.bbytes = (size_t)bo * (bf ? 4 : 8);
   // caller's flat layout
@@ -205,20 +222,26 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
 }
 
 // Work decomposition of the fused evaluation.
+// LDS placement of the packed BF16 weights of one ansatz.
+struct StagePlan {
+  int32_t frag[kMaxLayers];   // fragment offset of layer l in LDS, -1: global memory
+  size_t wbytes;              // staged weight bytes (aligned)
+  bool any;                   // at least one layer staged
+};
+
 struct EvalPlan {
   uint32_t rows_per_tile, tpi, ips;
   int64_t n_items;
   bool ldsw;
-  size_t lds_w;   // BF16: staged weight bytes (aligned); biases follow, then the wave contexts
-  uint32_t lds_l0;   // BF16 partial staging: layer 0 staged too
+  StagePlan stage;  // BF16: which layers are staged (biases follow the weights, then the
+                    // wave contexts and the input table)
+  bool inplace;     // BF16: hidden layers updated in place (see inplace_ok)
   size_t lds;
   int waves;        // waves per block
   unsigned grid;
 };
 
 constexpr size_t kLdsBytes = 160 * 1024;
-// per-wave LDS contexts of the BF16 kernel (every wave of a block)
-constexpr size_t kCtxBytesBF16 = kBlockLdsBF16;   // wave contexts + input table
 
 // Persistent grid: 32 waves per CU in total (a few rounds of resident blocks), unless tuned.
 int64_t grid_cap(const elocal_ctx* h, int waves) {
@@ -226,19 +249,52 @@ int64_t grid_cap(const elocal_ctx* h, int waves) {
   return (int64_t)h->cu_count * (32 / waves);
 }
 
-// Bytes of packed BF16 weights (aligned) a fused block of a width-`kernel_hmax` kernel
-// stages in LDS: all of them, or from kLdsPartialWidth on the output layer, followed by
-// layer 0 if both fit beside the biases and the wave contexts (*l0 = 1).
-static size_t staged_wbytes(const AnsatzGeom& G, int kernel_hmax, uint32_t* l0) {
-  *l0 = 0;
-  if (kernel_hmax < kLdsPartialWidth) return align256(G.wbytes);
+// Which layers a fused block of a width-`kernel_hmax` kernel with `waves` waves stages in
+// LDS beside `bias_bytes` of biases and the wave contexts: the whole network when it fits
+// (layers at their packed offsets); otherwise, from kLdsPartialWidth on, the output layer
+// (read once per output block by every tile) and then the other layers, largest first,
+// while they fit; below that width nothing.
+static StagePlan plan_stage(const AnsatzGeom& G, int kernel_hmax, int waves, size_t bias_bytes) {
+  StagePlan sp{};
   const MadeDev& M = G.md;
-  const size_t out = (size_t)(M.nfrag - M.woff[M.L]) * 64 * 16, first = (size_t)M.woff[1] * 64 * 16;
-  if (align256(out + first) + align256(G.bbytes) + kCtxBytesBF16 <= kLdsBytes) {
-    *l0 = 1;
-    return align256(out + first);
+  for (int l = 0; l < kMaxLayers; ++l) sp.frag[l] = -1;
+  const size_t fixed = align256(bias_bytes) + block_lds_bf16(waves);
+  if (fixed > kLdsBytes) return sp;
+  const size_t room = kLdsBytes - fixed;
+  if (align256(G.wbytes) <= room) {
+    for (int l = 0; l <= M.L; ++l) sp.frag[l] = M.foff[l][0];
+    sp.wbytes = align256(G.wbytes);
+    sp.any = true;
+    return sp;
   }
-  return align256(out);
+  if (kernel_hmax < kLdsPartialWidth) return sp;
+  int order[kMaxLayers], n = 0;
+  order[n++] = M.L;
+  for (int l = 0; l < M.L; ++l) order[n++] = l;
+  auto frags = [&](int l) { return M.foff[l][M.nob[l]] - M.foff[l][0]; };
+  std::stable_sort(order + 1, order + n, [&](int a, int b) { return frags(a) > frags(b); });
+  int32_t used = 0;
+  for (int i = 0; i < n; ++i) {
+    const int l = order[i];
+    if (align256((size_t)(used + frags(l)) * 1024) <= room) {
+      sp.frag[l] = used;
+      used += frags(l);
+    }
+  }
+  sp.wbytes = align256((size_t)used * 1024);
+  sp.any = used > 0;
+  return sp;
+}
+
+// In-place hidden layers are exact when o-block pair j of every hidden layer reads no
+// k-block beyond j + 1 (its second block's kend <= j + 2).
+static bool inplace_ok(const MadeDev& M) {
+  for (int l = 1; l < M.L; ++l)
+    for (int j = 0; 2 * j < M.nob[l]; ++j) {
+      const int ke = std::max(M.kend[l][2 * j], 2 * j + 1 < M.nob[l] ? M.kend[l][2 * j + 1] : 0);
+      if (ke > j + 2) return false;
+    }
+  return true;
 }
 
 EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t list_len = -1) {
@@ -252,12 +308,13 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
   const uint64_t per_item = (uint64_t)p.rows_per_tile * p.tpi;
   p.ips = (uint32_t)((rows + per_item - 1) / per_item);
   p.n_items = (int64_t)p.ips * B;
+  for (int l = 0; l < kMaxLayers; ++l) p.stage.frag[l] = -1;
   if (G.precision == ELOCAL_BF16) {
-    p.lds_w = staged_wbytes(G, G.hmax, &p.lds_l0);
-    const size_t need = p.lds_w + align256(G.bbytes) + kCtxBytesBF16;
-    p.ldsw = need <= kLdsBytes;   // one block per CU owns the CU's LDS
-    p.lds = p.ldsw ? need : kCtxBytesBF16;
     p.waves = eval_waves_bf16(G.hmax, G.nterms);
+    p.stage = plan_stage(G, G.hmax, p.waves, G.bbytes);
+    p.ldsw = p.stage.any;   // one block per CU owns the CU's LDS
+    p.lds = (p.ldsw ? p.stage.wbytes + align256(G.bbytes) : 0) + block_lds_bf16(p.waves);
+    p.inplace = inplace_kernel_bf16(G.hmax, G.nterms) && inplace_ok(G.md);
   } else {
     p.ldsw = false;
     p.lds = 0;
@@ -266,6 +323,15 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
   const int64_t want = (p.n_items + p.waves - 1) / p.waves;
   p.grid = (unsigned)std::max<int64_t>(1, std::min(want, grid_cap(h, p.waves)));
   return p;
+}
+
+// The LDS layout fields of the BF16 kernel arguments for a plan.
+void set_lds_args(EvalArgs& E, const EvalPlan& p, size_t bias_bytes) {
+  const size_t wb = p.ldsw ? p.stage.wbytes : 0, bb = p.ldsw ? align256(bias_bytes) : 0;
+  E.lds_bias_off = (uint32_t)wb;
+  E.lds_ctx_off = (uint32_t)(wb + bb);
+  E.lds_lut_off = (uint32_t)(wb + bb + (size_t)p.waves * kWaveCtxBytesBF16);
+  for (int l = 0; l < kMaxLayers; ++l) E.lds_frag[l] = p.ldsw ? p.stage.frag[l] : -1;
 }
 
 struct EvalWs {
@@ -572,15 +638,8 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
   const int slot = (int)(h->ring_pos % elocal_ctx::kRing);
   if (timed) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
   if (G.precision == ELOCAL_BF16) {
-    if (p.ldsw) {
-      E.lds_bias_off = (uint32_t)p.lds_w;
-      E.lds_ctx_off = (uint32_t)(p.lds_w + align256(G.bbytes));
-      E.lds_l0 = p.lds_l0;
-    } else {
-      E.lds_bias_off = 0;
-      E.lds_ctx_off = 0;
-    }
-    HIP_TRY(launch_eval_bf16(E, G.hmax, G.nterms, p.ldsw, p.lds, p.grid, st), "eval launch");
+    set_lds_args(E, p, G.bbytes);
+    HIP_TRY(launch_eval_bf16(E, G.hmax, G.nterms, p.ldsw, p.inplace, p.lds, p.grid, st), "eval launch");
   } else {
     HIP_TRY(launch_eval_f64(E, G.hmax, p.grid, st), "eval launch");
   }
@@ -605,9 +664,10 @@ struct MultiPlan {
   size_t args_off, first_off, bytes;
   int64_t first[ELOCAL_MAX_SYSTEMS + 1];
   int hmax, precision;
-  bool ldsw;            // BF16: every system's staged weights fit in LDS
-  uint32_t l0[ELOCAL_MAX_SYSTEMS];   // BF16 partial staging: system s stages layer 0 too
-  uint32_t bias_off, ctx_off;
+  bool ldsw;            // BF16: some system stages weights in LDS
+  bool inplace;         // BF16: in-place hidden layers (every system allows them)
+  StagePlan stage[ELOCAL_MAX_SYSTEMS];   // BF16: system s's staged layers
+  uint32_t bias_off, ctx_off, lut_off;   // BF16: the LDS layout every system shares
   size_t lds;
   unsigned grid;
 };
@@ -650,22 +710,27 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   const int unit = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax, M.G[0].nterms) : 1;
   M.first[0] = 0;
   for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
-  size_t wmax = 0, bmax = 0;
-  for (int s = 0; s < n_sys; ++s) {
-    M.l0[s] = 0;
-    if (M.precision != ELOCAL_BF16) continue;
-    wmax = std::max(wmax, staged_wbytes(M.G[s], M.hmax, &M.l0[s]));
-    bmax = std::max(bmax, align256(M.G[s].bbytes));
-  }
+  M.ldsw = M.inplace = false;
+  M.bias_off = M.ctx_off = M.lut_off = 0;
+  M.lds = 0;
   if (M.precision == ELOCAL_BF16) {
-    M.ldsw = wmax + bmax + kCtxBytesBF16 <= kLdsBytes;
-    M.bias_off = M.ldsw ? (uint32_t)wmax : 0;
-    M.ctx_off = M.ldsw ? (uint32_t)(wmax + bmax) : 0;
-    M.lds = M.ctx_off + kCtxBytesBF16;
-  } else {
-    M.ldsw = false;
-    M.bias_off = M.ctx_off = 0;
-    M.lds = 0;
+    // one LDS layout for all systems, sized for the kernel's width class and wave count
+    const int waves = eval_waves_bf16(M.hmax, M.G[0].nterms);
+    size_t wmax = 0, bmax = 0;
+    for (int s = 0; s < n_sys; ++s) bmax = std::max(bmax, align256(M.G[s].bbytes));
+    M.inplace = inplace_kernel_bf16(M.hmax, M.G[0].nterms);
+    for (int s = 0; s < n_sys; ++s) {
+      M.stage[s] = plan_stage(M.G[s], M.hmax, waves, bmax);
+      M.ldsw = M.ldsw || M.stage[s].any;
+      wmax = std::max(wmax, M.stage[s].wbytes);
+      M.inplace = M.inplace && inplace_ok(M.G[s].md);
+    }
+    if (M.ldsw) {
+      M.bias_off = (uint32_t)wmax;
+      M.ctx_off = (uint32_t)(wmax + bmax);
+    }
+    M.lut_off = M.ctx_off + (uint32_t)((size_t)waves * kWaveCtxBytesBF16);
+    M.lds = M.ctx_off + block_lds_bf16(waves);
   }
   M.args_off = off;
   off = align256(off + kArgsStride * n_sys);
@@ -731,7 +796,8 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
     E.sys = h->sys; E.made = M.G[i].md; E.made.wfrag = W[i].frag; E.made.bias = W[i].bias;
     E.x = x[i]; E.B = B[i]; E.ediag = W[i].ediag; E.F = W[i].F; E.lpx = W[i].lpx; E.lpx64 = W[i].lpx64;
     E.zphi = W[i].zphi; E.partial = W[i].partial; E.n_items = M.p[i].n_items; E.ips = M.p[i].ips;
-    E.tpi = M.p[i].tpi; E.lds_bias_off = 0; E.lds_ctx_off = 0; E.lds_l0 = M.l0[i];
+    E.tpi = M.p[i].tpi; E.lds_bias_off = M.bias_off; E.lds_ctx_off = M.ctx_off; E.lds_lut_off = M.lut_off;
+    for (int l = 0; l < kMaxLayers; ++l) E.lds_frag[l] = M.ldsw ? M.stage[i].frag[l] : -1;
     HIP_TRY(launch_store_bytes(&E, sizeof(EvalArgs), (char*)d_args + kArgsStride * k, st), "argument store");
   }
   HIP_TRY(launch_store_bytes(M.first, sizeof(int64_t) * (n_sys + 1), d_first, st), "argument store");
@@ -741,7 +807,7 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
   if (M.first[n_sys] > 0) {
     if (timed) HIP_TRY(hipEventRecord(h0->ev_start[slot], st), "timing event");
     if (M.precision == ELOCAL_BF16)
-      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.G[0].nterms, M.ldsw, M.lds, M.bias_off, M.ctx_off,
+      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.G[0].nterms, M.ldsw, M.inplace, M.lds,
                                      M.grid, st),
               "multi eval launch");
     else
@@ -921,9 +987,7 @@ elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz
   EvalArgs E{};
   E.sys = h->sys; E.made = M; E.x = x; E.B = B; E.ediag = w.ediag; E.F = w.F; E.lpx = w.lpx; E.zphi = w.zphi;
   E.partial = w.partial; E.n_items = p.n_items; E.ips = p.ips; E.tpi = p.tpi;
-  E.lds_bias_off = p.ldsw ? (uint32_t)p.lds_w : 0;
-  E.lds_ctx_off = p.ldsw ? (uint32_t)(p.lds_w + align256(G.bbytes)) : 0;
-  E.lds_l0 = p.lds_l0;
+  set_lds_args(E, p, G.bbytes);
   E.pl_mask = h->d_pl_mask; E.pl_off = h->d_pl_off; E.pl_z = h->d_pl_z; E.pl_coef = h->d_pl_coef;
   E.pl_len = (uint32_t)h->pl_len;
   const bool timed = h->timing && p.n_items > 0;

@@ -75,9 +75,12 @@ struct MadeDev {
   uint32_t nfrag;              // total fragments
   uint32_t nbias;              // total padded biases
   // BF16 packing stores hidden units sorted by degree; o-block ob of layer l then only
-  // needs its first kend[l][ob] k-blocks (the rest of its weights are masked).
+  // needs its first kend[l][ob] k-blocks (the rest of its weights are masked), and only
+  // those are stored: fragment kb < kend[l][ob] of o-block ob is foff[l][ob] + kb, and
+  // layer l occupies fragments [foff[l][0], foff[l][nob[l]]).
   // (32-bit so that a wave-uniform lookup is a scalar load)
   int32_t kend[kMaxLayers][kMaxOutBlocks];
+  int32_t foff[kMaxLayers][kMaxOutBlocks + 1];
   const void* wfrag;           // packed weights (8 fp16 per lane or one double per lane)
   const void* bias;            // float (BF16 mode) or double (FP64 mode)
 };
@@ -278,7 +281,9 @@ __device__ __forceinline__ void build_ctx(const SysDev& S, const uint64_t (&x)[N
     if (oa) c.occ[0][ia] = (uint8_t)p; else c.vir[0][p - ia] = (uint8_t)p;
     if (ob) c.occ[1][ib] = (uint8_t)p; else c.vir[1][p - ib] = (uint8_t)p;
   }
-  if (lane < NW) c.x[lane] = x[lane];
+#pragma unroll
+  for (int w = 0; w < NW; ++w)   // static indices: x stays in registers
+    if (lane == w) c.x[w] = x[w];
 }
 
 // Diagonal energy and the value of every single excitation of one sample (one wave; the

@@ -26,10 +26,11 @@ struct EvalArgs {
   int64_t n_items;
   uint32_t ips;            // work items per sample
   uint32_t tpi;            // row tiles per work item
-  uint32_t lds_bias_off;   // byte offset of the biases in LDS (weights at 0)
+  uint32_t lds_bias_off;   // byte offset of the biases in LDS (staged weights from 0)
   uint32_t lds_ctx_off;    // byte offset of the per-wave contexts
-  uint32_t lds_l0;         // partial staging (width >= kLdsPartialWidth): layer 0 staged after
-                           // the output layer (1) or read from global memory (0)
+  uint32_t lds_lut_off;    // byte offset of the input-expansion table
+  int32_t lds_frag[kMaxLayers];   // BF16: fragment offset of layer l's weights in LDS, or -1
+                                  // when the layer is read from global memory
   // Pauli-string route only: unique flip masks [pl_len], string offsets [pl_len + 1],
   // string Z masks and real coefficients [pl_off[pl_len]]
   const uint64_t* pl_mask;
@@ -67,8 +68,8 @@ hipError_t launch_check(const SysDev& S, const uint64_t* x, int64_t B, unsigned 
 hipError_t launch_pack_bf16(const MadeDev& M, const ThetaLayout& T, const uint16_t* theta,
                             void* frag, float* bias, hipStream_t st);
 hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t st);
-hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, size_t lds_bytes,
-                            unsigned grid, hipStream_t st);
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, bool inplace,
+                            size_t lds_bytes, unsigned grid, hipStream_t st);
 
 // Shape of the BF16 fused kernels (single and multi-system), one block per CU. With two
 // fp16 terms per activation a pass of the network takes one 16-row tile, so that a wave
@@ -85,17 +86,22 @@ constexpr int kMaxEvalWavesBF16 = 16;
 // the FP64 suffix sums of its per-orbital log2 probabilities.
 constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(double);
 // Input-expansion table of the fused BF16 kernels, in LDS after the wave contexts: entry v
-// holds the 8 fp16 values (bit j of v ? 1 : 0), the layer-0 operand of 8 input bits.
-constexpr size_t kXLutBytes = 256 * 16;
-// Fused BF16 kernels of at least this width stage only the output layer, followed by
-// layer 0 when it fits too, in LDS (their hidden layers do not fit) and read the rest
-// from global memory.
+// holds the 4 fp16 values (bit j of v ? 1 : 0); two entries form the layer-0 operand of 8
+// input bits.
+constexpr size_t kXLutBytes = 16 * 8;
+// Fused BF16 kernels of at least this width do not hold the whole network in LDS: the host
+// stages the layers that fit (the output layer first, then the largest others) and the
+// rest is read from global memory with loads issued ahead of the products.
 constexpr int kLdsPartialWidth = 256;
-// LDS a fused BF16 block needs beyond the staged weights and biases.
-constexpr size_t kBlockLdsBF16 = kMaxEvalWavesBF16 * kWaveCtxBytesBF16 + kXLutBytes;
+// LDS a fused BF16 block of `waves` waves needs beyond the staged weights and biases.
+constexpr size_t block_lds_bf16(int waves) { return (size_t)waves * kWaveCtxBytesBF16 + kXLutBytes; }
+// Hidden layers updated in place (INPLACE) exist for the widest two-term kernels, whose
+// waves run two per SIMD in 256 registers; the host uses them when every hidden layer's
+// o-block pair j reads no k-block beyond j + 1.
+constexpr bool inplace_kernel_bf16(int hmax, int nterms) { return hmax >= kLdsPartialWidth && nterms == 2; }
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system
 // s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax, nterms) work items each (LDS layout as
-// for one system: weights at 0, biases at bias_off, wave contexts at ctx_off). FP64:
+// for one system, with the bias, context and table offsets of args[0] for all). FP64:
 // system s owns work items [first[s], first[s+1]).
 hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, size_t lds_bytes,
                                   unsigned grid, hipStream_t st);
@@ -103,8 +109,7 @@ hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool 
 hipError_t launch_pauli_diag(const uint64_t* x, int64_t B, const uint32_t* off, const uint64_t* z,
                              const double* coef, double* ediag, hipStream_t st);
 hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
-                                  bool ldsw, size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid,
-                                  hipStream_t st);
+                                  bool ldsw, bool inplace, size_t lds, unsigned grid, hipStream_t st);
 hipError_t launch_eval_multi_f64(const EvalArgs* args, const int64_t* first, int n_sys, int hmax,
                                  unsigned grid, hipStream_t st);
 // Host record (bytes a multiple of 4) -> device memory, in stream order.

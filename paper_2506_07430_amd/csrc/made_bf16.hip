@@ -61,18 +61,20 @@ __device__ __forceinline__ unsigned short f16_bits_of_bf16(unsigned short b) {
 }
 
 // Packs the caller's parameters (bf16 bit patterns, natural order) into fp16 MFMA A-operand
-// fragments with hidden units in degree order, masked entries zeroed; biases to FP32.
+// fragments (only the k-blocks each o-block uses) with hidden units in degree order, masked
+// entries zeroed; biases to FP32.
 __global__ void k_pack_bf16(MadeDev M, ThetaLayout T, const uint16_t* __restrict__ theta,
                             h16x8* __restrict__ frag, float* __restrict__ bias) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = M.n, L = M.L;
   if (gid < M.nfrag * 64u) {
-    const uint32_t f = gid >> 6;
+    const int32_t f = (int32_t)(gid >> 6);
     const int lane = gid & 63;
     int l = 0;
-    while (l < L && f >= M.woff[l + 1]) ++l;
-    const uint32_t local = f - M.woff[l];
-    const int ob = local / M.nk[l], kb = local % M.nk[l];
+    while (l < L && f >= M.foff[l + 1][0]) ++l;
+    int ob = 0;
+    while (ob + 1 < M.nob[l] && f >= M.foff[l][ob + 1]) ++ob;
+    const int kb = f - M.foff[l][ob];
     const int orow = 16 * ob + (lane & 15), g = lane >> 4;
     // original output unit of this row
     const int o = (l < L) ? (orow < M.nout[l] ? sorted_unit(n, M.nout[l], orow) : -1)
@@ -195,47 +197,39 @@ __device__ __forceinline__ f32x4 load_bias4(const float* bias, uint32_t off) {
 
 // Every block sees at least its first k-block (kend >= 1, checked when the ansatz is
 // packed), so k-block 0 is issued unconditionally in the layers below.
+//
+// Packing: only the k-blocks an o-block uses are stored, o-block after o-block, so
+// fragment kb of o-block ob of layer l is M.foff[l][ob] + kb (kb < kend[l][ob]).
+// Where a layer's fragments are read from: LDS when the layer is staged there (lds[l] >= 0
+// is then the fragment offset of its first fragment in LDS), else global memory. Each
+// layer's code is generated for both sources, so LDS reads are LDS instructions.
+template <class Body>
+__device__ __forceinline__ void with_layer(const MadeDev& M, const int32_t* lds, const unsigned char* smem, int l,
+                                           Body&& body) {
+  const int32_t lf = lds ? sgpr(lds[l]) : -1;
+  if (lf >= 0) {
+    body((const h16x8*)smem + (size_t)lf * 64 - (size_t)M.foff[l][0] * 64, std::true_type{});
+  } else {
+    body((const h16x8*)M.wfrag, std::false_type{});
+  }
+}
 
-// Where the packed weights are read from: layer 0 and the output layer each from its own
-// base (fragment 0 of the layer), the hidden layers from a base indexed by woff[l]. All
-// three point into LDS when the whole network is staged; with partial staging (width 256,
-// whose hidden layers do not fit) the output layer is in LDS, followed by layer 0 when it
-// fits too (then read through a generic pointer), and the hidden layers in global memory.
-struct WeightsBF16 {
-  const h16x8* hid;
-  const h16x8* l0;
-  const h16x8* out;
-};
-
-// Partial staging (layer 0 and the output layer only) for the widest networks.
+// Partial staging (the whole network does not fit in LDS) for the widest networks: their
+// global-memory layers issue weight loads ahead of the products.
 template <int HMAX>
 constexpr bool lds_partial_bf16() { return HMAX >= kLdsPartialWidth; }
 
-__device__ __forceinline__ WeightsBF16 weights_global(const MadeDev& M) {
-  const h16x8* W = (const h16x8*)M.wfrag;
-  return {W, W, W + (size_t)M.woff[M.L] * 64};
-}
-
-template <int HMAX>
-__device__ __forceinline__ WeightsBF16 weights_lds(const MadeDev& M, const unsigned char* smem, uint32_t l0) {
-  const h16x8* S = (const h16x8*)smem;
-  if (lds_partial_bf16<HMAX>()) {
-    const h16x8* G = (const h16x8*)M.wfrag;
-    return {G, l0 ? S + (size_t)(M.nfrag - M.woff[M.L]) * 64 : G, S};
-  }
-  return {S, S, S + (size_t)M.woff[M.L] * 64};
-}
-
 // Output block ob of the last layer for the NC 16-row tiles (tile c: row r of lane r).
+// W: base such that fragment f of the packing is W[f * 64 + lane].
 template <int KB, int NT, int NC>
-__device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restrict__ WL,
+__device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restrict__ W,
                                           const float* __restrict__ bias, const h16x8 (&act)[NT][NC][KB],
                                           int ob, int lane, f32x4 (&a)[NC]) {
-  const int l = M.L, nk = M.nk[l], ke = sgpr(M.kend[l][ob]);
+  const int l = M.L, ke = sgpr(M.kend[l][ob]);
   const f32x4 b4 = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
 #pragma unroll
   for (int c = 0; c < NC; ++c) a[c] = b4;
-  const h16x8* wp = WL + (size_t)(ob * nk) * 64 + lane;
+  const h16x8* wp = W + (size_t)sgpr(M.foff[l][ob]) * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     if (kb == 0 || kb < ke) {
@@ -248,74 +242,94 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restr
   }
 }
 
-// Runs the network on NC 16-row tiles (tile c: row r of lane r) and calls epi(ob, a[NC])
-// for the output blocks ob >= ob_first (earlier blocks belong
-// to orbitals the caller does not need). Hidden activations are carried as NT bf16
-// terms (one MFMA per term and weight fragment).
-// With XLUT the layer-0 operands come from the LDS table xlut (kXLutBytes), else they are
-// expanded from the bits in registers.
-template <int HMAX, int NW, int NT, int NC, bool XLUT = false, class Epi>
-__device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt,
-                                         const float* __restrict__ bias,
-                                         const uint64_t (&xr)[NC][NW], int lane, int ob_first,
-                                         const h16x8* xlut, Epi&& epi) {
-  constexpr int KB = HMAX / 32;
-  const int g = lane >> 4;
-  h16x8 act[NT][NC][KB];
-  // ---- layer 0: exact 0/1 inputs, one MFMA per fragment
-  {
-    const int nk = M.nk[0], nob = M.nob[0];
-    h16x8 xin[NC][4];
+// Products of o-block pair (2 kbo, 2 kbo + 1) of hidden layer l >= 1 over the k-blocks its
+// mask keeps, into a0 (block 2 kbo) and a1 (block 2 kbo + 1), which arrive holding the
+// biases. With PREFETCH (NT = 2) the fragment loads are issued in chunks of four k-blocks,
+// one chunk ahead of the products.
+template <int KB, int NT, int NC, bool PREFETCH>
+__device__ __forceinline__ void hidden_pair(const MadeDev& M, const h16x8* __restrict__ W, int l, int kbo,
+                                            const h16x8 (&act)[NT][NC][KB], int lane, f32x4 (&a0)[NC],
+                                            f32x4 (&a1)[NC]) {
+  const int ke0 = sgpr(M.kend[l][2 * kbo]), ke1 = sgpr(M.kend[l][2 * kbo + 1]);
+  const h16x8* w0p = W + (size_t)sgpr(M.foff[l][2 * kbo]) * 64 + lane;
+  const h16x8* w1p = W + (size_t)sgpr(M.foff[l][2 * kbo + 1]) * 64 + lane;
+  if constexpr (PREFETCH) {
+    constexpr int CH = 4, NCH = (KB + CH - 1) / CH;
+    h16x8 w0b[NCH][CH], w1b[NCH][CH];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int j = 0; j < CH; ++j) {   // prologue: chunk 0
+      const int kb = j;
+      if (kb == 0 || kb < ke1) w1b[0][j] = w1p[kb * 64];
+      if (kb == 0 || kb < ke0) w0b[0][j] = w0p[kb * 64];
+    }
 #pragma unroll
-      for (int kb = 0; kb < 4; ++kb)
-        if (XLUT) xin[c][kb] = xlut[kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u];
-        else xin[c][kb] = bits_to_h16x8(kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u);
+    for (int c = 0; c < NCH; ++c) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (c * CH < ke1) {
+        if (c + 1 < NCH) {
 #pragma unroll
-    for (int kbo = 0; kbo < KB; ++kbo) {
-      if (2 * kbo < nob) {
-        const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
-        f32x4 a0[NC], a1[NC];
-        {
-          const f32x4 b0 = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
-          const f32x4 b1 = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
-        }
-        const h16x8* w0p = Wt.l0 + (size_t)((2 * kbo) * nk) * 64 + lane;
-        const h16x8* w1p = w0p + (size_t)nk * 64;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-          if (kb == 0 || kb < ke1) {
-            const h16x8 w1 = w1p[kb * 64];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(w1, xin[c][kb], a1[c]);
-            if (kb == 0 || kb < ke0) {
-              const h16x8 w0 = w0p[kb * 64];
-#pragma unroll
-              for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
-            }
+          for (int j = 0; j < CH; ++j) {
+            const int kb = (c + 1) * CH + j;
+            if (kb < ke1) w1b[c + 1][j] = w1p[kb * 64];
+            if (kb < ke0) w0b[c + 1][j] = w0p[kb * 64];
           }
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          h16x8 t[NT];
-          split_relu<NT>(a0[c], a1[c], t);
+        for (int j = 0; j < CH; ++j) {
+          const int kb = c * CH + j;
+          if (kb < KB && (kb == 0 || kb < ke1)) {
 #pragma unroll
-          for (int i = 0; i < NT; ++i) act[i][c][kbo] = t[i];
+            for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+              for (int i = 0; i < NT; ++i) a1[cc] = mfma_f16(w1b[c][j], act[i][cc][kb], a1[cc]);
+            if (kb == 0 || kb < ke0) {
+#pragma unroll
+              for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+                for (int i = 0; i < NT; ++i) a0[cc] = mfma_f16(w0b[c][j], act[i][cc][kb], a0[cc]);
+            }
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      if (kb == 0 || kb < ke1) {
+        const h16x8 w1 = w1p[kb * 64];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int i = 0; i < NT; ++i) a1[c] = mfma_f16(w1, act[i][c][kb], a1[c]);
+        if (kb == 0 || kb < ke0) {
+          const h16x8 w0 = w0p[kb * 64];
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int i = 0; i < NT; ++i) a0[c] = mfma_f16(w0, act[i][c][kb], a0[c]);
         }
       }
     }
   }
-  // ---- hidden layers 1..L-1
-  for (int l = 1; l < M.L; ++l) {
-    const int nk = M.nk[l], nob = M.nob[l];
-    h16x8 nxt[NT][NC][KB];
+}
+
+// Hidden layer l >= 1. Without INPLACE the outputs go to a second activation array. With
+// INPLACE they overwrite the inputs: pairs run from the last to the first, and the
+// result of pair j is held back until pair j - 1 is done, then stored in k-slot j. This
+// is exact when no pair j reads beyond k-block j + 1 (kend of its second block <= j + 2,
+// which the host checks for every hidden layer): pair j then never sees a slot that was
+// already overwritten, and slot j + 1 is free once pair j is done.
+template <int HMAX, int NT, int NC, bool INPLACE, bool PREFETCH>
+__device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __restrict__ W,
+                                             const float* __restrict__ bias, int l, int lane,
+                                             h16x8 (&act)[NT][NC][HMAX / 32]) {
+  constexpr int KB = HMAX / 32;
+  const int g = lane >> 4, nob = M.nob[l];
+  if constexpr (INPLACE) {
+    h16x8 pend[NT][NC];
 #pragma unroll
-    for (int kbo = 0; kbo < KB; ++kbo) {
+    for (int kbo = KB - 1; kbo >= 0; --kbo) {
       if (2 * kbo < nob) {
-        const int ke0 = sgpr(M.kend[l][2 * kbo]), ke1 = sgpr(M.kend[l][2 * kbo + 1]);
         f32x4 a0[NC], a1[NC];
         {
           const f32x4 b0 = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
@@ -323,71 +337,39 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        const h16x8* w0p = Wt.hid + (size_t)(M.woff[l] + (2 * kbo) * nk) * 64 + lane;
-        const h16x8* w1p = w0p + (size_t)nk * 64;
-        if constexpr (lds_partial_bf16<HMAX>() && NT == 2) {
-          // hidden weights from global memory (few waves per SIMD): a pair's loads are issued
-          // in chunks of CH k-blocks, one chunk ahead of the products (the three-term mode has
-          // no registers left for this)
-          constexpr int CH = 4, NCH = KB / CH;
-          h16x8 w0b[NCH][CH], w1b[NCH][CH];
+        hidden_pair<KB, NT, NC, PREFETCH>(M, W, l, kbo, act, lane, a0, a1);
+        if (kbo + 1 < KB && 2 * (kbo + 1) < nob) {
 #pragma unroll
-          for (int c = 0; c < 1 && c < NCH; ++c)   // prologue: chunk 0
+          for (int i = 0; i < NT; ++i)
 #pragma unroll
-            for (int j = 0; j < CH; ++j) {
-              const int kb = c * CH + j;
-              if (kb == 0 || kb < ke1) w1b[c][j] = w1p[kb * 64];
-              if (kb == 0 || kb < ke0) w0b[c][j] = w0p[kb * 64];
-            }
-#pragma unroll
-          for (int c = 0; c < NCH; ++c) {
-            __builtin_amdgcn_sched_barrier(0);
-            if (c * CH < ke1) {
-              if (c + 1 < NCH) {
-#pragma unroll
-                for (int j = 0; j < CH; ++j) {
-                  const int kb = (c + 1) * CH + j;
-                  if (kb < ke1) w1b[c + 1][j] = w1p[kb * 64];
-                  if (kb < ke0) w0b[c + 1][j] = w0p[kb * 64];
-                }
-              }
-#pragma unroll
-              for (int j = 0; j < CH; ++j) {
-                const int kb = c * CH + j;
-                if (kb == 0 || kb < ke1) {
-#pragma unroll
-                  for (int cc = 0; cc < NC; ++cc)
-#pragma unroll
-                    for (int i = 0; i < NT; ++i) a1[cc] = mfma_f16(w1b[c][j], act[i][cc][kb], a1[cc]);
-                  if (kb == 0 || kb < ke0) {
-#pragma unroll
-                    for (int cc = 0; cc < NC; ++cc)
-#pragma unroll
-                      for (int i = 0; i < NT; ++i) a0[cc] = mfma_f16(w0b[c][j], act[i][cc][kb], a0[cc]);
-                  }
-                }
-              }
-            }
-          }
-        } else {
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          if (kb == 0 || kb < ke1) {
-            const h16x8 w1 = w1p[kb * 64];
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-              for (int i = 0; i < NT; ++i) a1[c] = mfma_f16(w1, act[i][c][kb], a1[c]);
-            if (kb == 0 || kb < ke0) {
-              const h16x8 w0 = w0p[kb * 64];
-#pragma unroll
-              for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int i = 0; i < NT; ++i) a0[c] = mfma_f16(w0, act[i][c][kb], a0[c]);
-            }
-          }
+            for (int c = 0; c < NC; ++c) act[i][c][kbo + 1 < KB ? kbo + 1 : 0] = pend[i][c];
         }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          h16x8 t[NT];
+          split_relu<NT>(a0[c], a1[c], t);
+#pragma unroll
+          for (int i = 0; i < NT; ++i) pend[i][c] = t[i];
         }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) act[i][c][0] = pend[i][c];
+  } else {
+    h16x8 nxt[NT][NC][KB];
+#pragma unroll
+    for (int kbo = 0; kbo < KB; ++kbo) {
+      if (2 * kbo < nob) {
+        f32x4 a0[NC], a1[NC];
+        {
+          const f32x4 b0 = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
+          const f32x4 b1 = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
+        }
+        hidden_pair<KB, NT, NC, PREFETCH>(M, W, l, kbo, act, lane, a0, a1);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           h16x8 t[NT];
@@ -404,16 +386,169 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const WeightsBF16& Wt
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) act[i][c][kb] = nxt[i][c][kb];
   }
-  // ---- output layer, block by block into the epilogue
+}
+
+// Runs the network on NC 16-row tiles (tile c: row r of lane r) and calls epi(ob, a[NC])
+// for the output blocks ob >= ob_first (earlier blocks belong to orbitals the caller does
+// not need). Hidden activations are carried as NT fp16 terms (one MFMA per term and
+// weight fragment). lds: per-layer LDS placement (see with_layer; nullptr: every layer in
+// global memory). With XLUT the layer-0 operands come from the LDS table xlut (16 entries
+// of 4 input bits), else they are expanded from the bits in registers.
+template <int HMAX, int NW, int NT, int NC, bool XLUT = false, bool INPLACE = false, class Epi>
+__device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, const unsigned char* smem,
+                                         const float* __restrict__ bias, const uint64_t (&xr)[NC][NW], int lane,
+                                         int ob_first, const uint64_t* xlut, Epi&& epi) {
+  constexpr int KB = HMAX / 32;
+  constexpr bool PF = lds_partial_bf16<HMAX>() && NT == 2;
+  const int g = lane >> 4;
+  h16x8 act[NT][NC][KB];
+  // ---- layer 0: exact 0/1 inputs, one MFMA per fragment
   {
-    const int nob = M.nob[M.L];
-#pragma unroll 1
-    for (int ob = sgpr(ob_first); ob < nob; ++ob) {
-      f32x4 acc[NC];
-      out_block<KB, NT, NC>(M, Wt.out, bias, act, ob, lane, acc);
-      epi(ob, acc);
-    }
+    const int nk = M.nk[0], nob = M.nob[0];
+    h16x8 xin[NC][4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const uint32_t b8 = kb < nk ? bits8_at<NW>(xr[c], 32 * kb + 8 * g) : 0u;
+        if (XLUT) {
+          const uint64_t w2[2] = {xlut[b8 & 15u], xlut[b8 >> 4]};
+          __builtin_memcpy(&xin[c][kb], w2, 16);
+        } else {
+          xin[c][kb] = bits_to_h16x8(b8);
+        }
+      }
+    with_layer(M, lds, smem, 0, [&](const h16x8* W, auto in_lds) {
+      // global memory with PF: the fragments of pair kbo + 1 are loaded while pair kbo is
+      // multiplied (two buffers, all of a pair's at most 4 k-blocks at once)
+      constexpr bool G0 = !decltype(in_lds)::value && PF;
+      h16x8 wb[G0 ? 2 : 1][2][4];
+      auto load_pair = [&](int kbo, h16x8 (&dst)[2][4]) {
+        const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
+        const h16x8* w0p = W + (size_t)sgpr(M.foff[0][2 * kbo]) * 64 + lane;
+        const h16x8* w1p = W + (size_t)sgpr(M.foff[0][2 * kbo + 1]) * 64 + lane;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          if (kb == 0 || kb < ke1) dst[1][kb] = w1p[kb * 64];
+          if (kb == 0 || kb < ke0) dst[0][kb] = w0p[kb * 64];
+        }
+      };
+      if constexpr (G0) load_pair(0, wb[0]);
+#pragma unroll
+      for (int kbo = 0; kbo < KB; ++kbo) {
+        if (2 * kbo < nob) {
+          const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
+          f32x4 a0[NC], a1[NC];
+          {
+            const f32x4 b0 = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
+            const f32x4 b1 = load_bias4(bias, M.boff[0] + 32 * kbo + 16 + 4 * g);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
+          }
+          if constexpr (G0) {
+            if (kbo + 1 < KB && 2 * (kbo + 1) < nob) load_pair(kbo + 1 < KB ? kbo + 1 : 0, wb[(kbo + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+              if (kb == 0 || kb < ke1) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(wb[kbo & 1][1][kb], xin[c][kb], a1[c]);
+                if (kb == 0 || kb < ke0) {
+#pragma unroll
+                  for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(wb[kbo & 1][0][kb], xin[c][kb], a0[c]);
+                }
+              }
+            }
+          } else {
+            const h16x8* w0p = W + (size_t)sgpr(M.foff[0][2 * kbo]) * 64 + lane;
+            const h16x8* w1p = W + (size_t)sgpr(M.foff[0][2 * kbo + 1]) * 64 + lane;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+              if (kb == 0 || kb < ke1) {
+                const h16x8 w1 = w1p[kb * 64];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(w1, xin[c][kb], a1[c]);
+                if (kb == 0 || kb < ke0) {
+                  const h16x8 w0 = w0p[kb * 64];
+#pragma unroll
+                  for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            h16x8 t[NT];
+            split_relu<NT>(a0[c], a1[c], t);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) act[i][c][kbo] = t[i];
+          }
+        }
+      }
+    });
   }
+  // ---- hidden layers 1..L-1
+  for (int l = 1; l < M.L; ++l) {
+    // the widest networks issue a chunk of fragment loads ahead of the products from LDS
+    // as from global memory (one wait per chunk instead of one per fragment)
+    with_layer(M, lds, smem, l, [&](const h16x8* W, auto) {
+      hidden_layer<HMAX, NT, NC, INPLACE, PF>(M, W, bias, l, lane, act);
+    });
+  }
+  // ---- output layer, block by block into the epilogue
+  with_layer(M, lds, smem, M.L, [&](const h16x8* W, auto) {
+    const int nob = M.nob[M.L];
+    if constexpr (PF) {
+      // the fragments of block ob + 1 are loaded while block ob is multiplied and its
+      // epilogue runs (two buffers, all of a block's k-blocks at once)
+      const int l = M.L;
+      h16x8 wv[2][KB];
+      auto load_block = [&](int ob, h16x8 (&dst)[KB]) {
+        const int ke = sgpr(M.kend[l][ob]);
+        const h16x8* wp = W + (size_t)sgpr(M.foff[l][ob]) * 64 + lane;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+          if (kb == 0 || kb < ke) dst[kb] = wp[kb * 64];
+      };
+      auto run_block = [&](int ob, const h16x8 (&wsrc)[KB]) {
+        const int ke = sgpr(M.kend[l][ob]);
+        f32x4 a[NC];
+        const f32x4 b4 = load_bias4(bias, M.boff[l] + 16 * ob + 4 * g);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c] = b4;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          if (kb == 0 || kb < ke) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+              for (int i = 0; i < NT; ++i) a[c] = mfma_f16(wsrc[kb], act[i][c][kb], a[c]);
+          }
+        }
+        epi(ob, a);
+      };
+      int ob = sgpr(ob_first);
+      if (ob < nob) load_block(ob, wv[0]);
+#pragma unroll 1
+      while (ob < nob) {
+        if (ob + 1 < nob) load_block(ob + 1, wv[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        run_block(ob, wv[0]);
+        if (++ob >= nob) break;
+        if (ob + 1 < nob) load_block(ob + 1, wv[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        run_block(ob, wv[1]);
+        ++ob;
+      }
+    } else {
+#pragma unroll 1
+      for (int ob = sgpr(ob_first); ob < nob; ++ob) {
+        f32x4 acc[NC];
+        out_block<KB, NT, NC>(M, W, bias, act, ob, lane, acc);
+        epi(ob, acc);
+      }
+    }
+  });
 }
 
 // Per-row state of the epilogue at the lane's current orbital p: the row's occupation
@@ -517,7 +652,6 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   if (b0 >= Bn) return;
   const MadeDev& M = P.made;
   const int n = P.sys.n, na = P.sys.na, nb = P.sys.nb;
-  const WeightsBF16 Wt = weights_global(M);
   const float* bias = (const float*)M.bias;
   uint64_t xr[2][NW];
   int64_t rb[2];
@@ -532,7 +666,7 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
   double A[2] = {0.0, 0.0};
   float zp[2] = {0.f, 0.f};
   RowCursor<NW> rc[2] = {cursor_at<NW>(xr[0], min(g, n - 1)), cursor_at<NW>(xr[1], min(g, n - 1))};
-  mlp_bf16<HMAX, NW, NT, 2>(M, Wt, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4 (&a)[2]) {
+  mlp_bf16<HMAX, NW, NT, 2>(M, nullptr, nullptr, bias, xr, lane, 0, nullptr, [&](int ob, const f32x4 (&a)[2]) {
     const int p = 4 * ob + g;
     if (p < n - 1) {   // the last orbital's conditional is 1
       const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
@@ -640,9 +774,9 @@ __device__ __attribute__((noinline)) double2 ratio_term(double hv, float zp, dou
 // network runs in 4 / NC passes of NC 16-row tiles over the 64 entries; every lane then
 // forms H exp(dA + i dphi) in FP64 for its own entry. The item's partial sum (fixed
 // order) goes to P.partial[item].
-template <int HMAX, int NW, int NT, class Gen = ScGen>
-__device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsBF16& Wt,
-                                               const float* __restrict__ bias, const h16x8* xlut,
+template <int HMAX, int NW, int NT, bool INPLACE = false, class Gen = ScGen>
+__device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t* lds, const unsigned char* smem,
+                                               const float* __restrict__ bias, const uint64_t* xlut,
                                                WaveCtxBF16& wc, int64_t item, SampleState<NW>& st, int lane) {
   constexpr int NC = eval_cols_bf16(HMAX, NT);
   const MadeDev& M = P.made;
@@ -717,7 +851,8 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
         zp[c] = 0.f;
         rc[c] = cursor_at<NW>(xr[c], pfirst);
       }
-      mlp_bf16<HMAX, NW, NT, NC, true>(M, Wt, bias, xr, lane, ob_first, xlut, [&](int ob, const f32x4 (&a)[NC]) {
+      mlp_bf16<HMAX, NW, NT, NC, true, INPLACE>(M, lds, smem, bias, xr, lane, ob_first, xlut,
+                                                 [&](int ob, const f32x4 (&a)[NC]) {
         const int p = 4 * ob + g;
         if (p < n - 1) {   // the last orbital's conditional is 1
           const int ta = na - (n - p - 1), tb = nb - (n - p - 1);
@@ -773,20 +908,17 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const WeightsB
 // Block shape of the fused kernels: one block per CU, so the whole 160 KiB of LDS can
 // hold the packed weights of one ansatz (waves per block: eval_waves_bf16).
 
-// Copies the packed weights (all of them, or with PARTIAL the output layer followed, if
-// l0, by layer 0) and the biases into LDS.
-template <bool PARTIAL>
-__device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* smem, uint32_t bias_off,
-                                              uint32_t l0) {
+// Copies the packed weights of every staged layer (lds[l] >= 0: fragment offset in LDS)
+// and the biases into LDS.
+__device__ __forceinline__ void stage_weights(const MadeDev& M, const int32_t* lds, unsigned char* smem,
+                                              uint32_t bias_off) {
   h16x8* sw = (h16x8*)smem;
   const h16x8* gw = (const h16x8*)M.wfrag;
-  if (PARTIAL) {
-    const uint32_t n0 = l0 ? M.woff[1] * 64u : 0u, nl = (M.nfrag - M.woff[M.L]) * 64u;
-    const h16x8* gl = gw + (size_t)M.woff[M.L] * 64;
-    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) sw[i] = gl[i];
-    for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) sw[nl + i] = gw[i];
-  } else {
-    for (uint32_t i = threadIdx.x; i < M.nfrag * 64u; i += blockDim.x) sw[i] = gw[i];
+  for (int l = 0; l <= M.L; ++l) {
+    const int32_t lf = lds[l];
+    if (lf < 0) continue;
+    const uint32_t f0 = (uint32_t)M.foff[l][0], nf = (uint32_t)M.foff[l][M.nob[l]] - f0;
+    for (uint32_t i = threadIdx.x; i < nf * 64u; i += blockDim.x) sw[(size_t)lf * 64 + i] = gw[(size_t)f0 * 64 + i];
   }
   float* sb = (float*)(smem + bias_off);
   const float* gb = (const float*)M.bias;
@@ -794,28 +926,29 @@ __device__ __forceinline__ void stage_weights(const MadeDev& M, unsigned char* s
 }
 
 // Fills the input-expansion table (every thread of the block takes part; the caller
-// synchronises the block before the table is read).
-__device__ __forceinline__ h16x8* fill_xlut(unsigned char* smem, uint32_t ctx_off) {
-  static_assert((kMaxEvalWavesBF16 * kWaveCtxBytesBF16) % 16 == 0, "input table alignment");
-  h16x8* lut = (h16x8*)(smem + ctx_off + kMaxEvalWavesBF16 * kWaveCtxBytesBF16);
-  for (uint32_t v = threadIdx.x; v < 256u; v += blockDim.x) lut[v] = bits_to_h16x8(v);
+// synchronises the block before the table is read): entry v (4 bits) holds the four fp16
+// values bit j of v ? 1 : 0.
+__device__ __forceinline__ uint64_t* fill_xlut(unsigned char* smem, uint32_t lut_off) {
+  uint64_t* lut = (uint64_t*)(smem + lut_off);
+  for (uint32_t v = threadIdx.x; v < 16u; v += blockDim.x) {
+    uint64_t e = 0;
+    for (int j = 0; j < 4; ++j) e |= (uint64_t)(((v >> j) & 1u) * 0x3C00u) << (16 * j);
+    lut[v] = e;
+  }
   return lut;
 }
 
 // One system; a persistent grid strides over the work items, one wave per item. With
-// LDSW the packed weights (at width 256 the output layer and, if it fits, layer 0) and
-// the biases are first staged in LDS.
-template <int HMAX, int NW, int NT, bool LDSW>
+// LDSW the layers the host placed in LDS (P.lds_frag) and the biases are first staged.
+template <int HMAX, int NW, int NT, bool LDSW, bool INPLACE>
 __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16(EvalArgs P) {
   constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
-  WeightsBF16 Wt = weights_global(P.made);
   const float* bias = (const float*)P.made.bias;
-  const h16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
+  const uint64_t* xlut = fill_xlut(smem, P.lds_lut_off);
   if (LDSW) {
-    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off, P.lds_l0);
-    Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
+    stage_weights(P.made, P.lds_frag, smem, P.lds_bias_off);
     bias = (const float*)(smem + P.lds_bias_off);
   }
   __syncthreads();
@@ -824,7 +957,7 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, NW, NT>(P, Wt, bias, xlut, wc, item, st, lane);
+    eval_item_bf16<HMAX, NW, NT, INPLACE>(P, LDSW ? P.lds_frag : nullptr, smem, bias, xlut, wc, item, st, lane);
 }
 
 // Pauli-string route: the fused kernel over the unique flip masks of every sample (one
@@ -834,12 +967,10 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
-  WeightsBF16 Wt = weights_global(P.made);
   const float* bias = (const float*)P.made.bias;
-  const h16x8* xlut = fill_xlut(smem, P.lds_ctx_off);
+  const uint64_t* xlut = fill_xlut(smem, P.lds_lut_off);
   if (LDSW) {
-    stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, P.lds_bias_off, P.lds_l0);
-    Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
+    stage_weights(P.made, P.lds_frag, smem, P.lds_bias_off);
     bias = (const float*)(smem + P.lds_bias_off);
   }
   __syncthreads();
@@ -848,29 +979,31 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, 1, NT, PauliGen>(P, Wt, bias, xlut, wc, item, st, lane);
+    eval_item_bf16<HMAX, 1, NT, false, PauliGen>(P, LDSW ? P.lds_frag : nullptr, smem, bias, xlut, wc, item, st,
+                                                 lane);
 }
 
 // Several systems in one persistent launch. Work is cut into chunks of kEvalWaves items
 // (one per wave of a block) that never straddle two systems; system s owns chunks
 // [first[s], first[s+1]). Blocks stride over the chunks, so every block's share mixes
 // the systems in proportion and no system leaves a tail of its own. With LDSW a block
-// restages the weights whenever its next chunk belongs to another system.
-template <int HMAX, int NT, bool LDSW>
+// restages the weights whenever its next chunk belongs to another system (every system's
+// staged layers, biases, wave contexts and input table share one LDS layout: the offsets
+// of system 0's arguments).
+template <int HMAX, int NT, bool LDSW, bool INPLACE>
 __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
-    k_eval_multi_bf16(const EvalArgs* __restrict__ args, const int64_t* __restrict__ first, int n_sys,
-                      uint32_t lds_bias_off, uint32_t lds_ctx_off) {
+    k_eval_multi_bf16(const EvalArgs* __restrict__ args, const int64_t* __restrict__ first, int n_sys) {
   constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
-  WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + lds_ctx_off))[wid];
+  const uint32_t bias_off = args[0].lds_bias_off, ctx_off = args[0].lds_ctx_off;
+  WaveCtxBF16& wc = ((WaveCtxBF16*)(smem + ctx_off))[wid];
   SampleState<1> st1;
   SampleState<2> st2;
   st1.b = st2.b = -1;
   int cur = -1;
-  WeightsBF16 Wt = {nullptr, nullptr, nullptr};
   const float* bias = nullptr;
-  const h16x8* xlut = fill_xlut(smem, lds_ctx_off);
+  const uint64_t* xlut = fill_xlut(smem, args[0].lds_lut_off);
   __syncthreads();
   const int64_t chunks = first[n_sys];
   for (int64_t chunk = blockIdx.x; chunk < chunks; chunk += gridDim.x) {
@@ -883,19 +1016,18 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
       st1.b = st2.b = -1;
       if (LDSW) {
         __syncthreads();   // every wave is done with the previous system's weights
-        stage_weights<lds_partial_bf16<HMAX>()>(P.made, smem, lds_bias_off, P.lds_l0);
+        stage_weights(P.made, P.lds_frag, smem, bias_off);
         __syncthreads();
-        Wt = weights_lds<HMAX>(P.made, smem, P.lds_l0);
-        bias = (const float*)(smem + lds_bias_off);
+        bias = (const float*)(smem + bias_off);
       } else {
-        Wt = weights_global(P.made);
         bias = (const float*)P.made.bias;
       }
     }
     const int64_t local = (chunk - first[s]) * kEvalWaves + wid;
     if (local < P.n_items) {
-      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT>(P, Wt, bias, xlut, wc, local, st1, lane);
-      else eval_item_bf16<HMAX, 2, NT>(P, Wt, bias, xlut, wc, local, st2, lane);
+      const int32_t* lds = LDSW ? P.lds_frag : nullptr;
+      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT, INPLACE>(P, lds, smem, bias, xlut, wc, local, st1, lane);
+      else eval_item_bf16<HMAX, 2, NT, INPLACE>(P, lds, smem, bias, xlut, wc, local, st2, lane);
     }
   }
 }
@@ -950,8 +1082,8 @@ hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t
   });
 }
 
-hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, size_t lds, unsigned grid,
-                            hipStream_t st) {
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, bool inplace, size_t lds,
+                            unsigned grid, hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
   return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
     constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
@@ -961,8 +1093,17 @@ hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, 
       hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, A);
       return hipGetLastError();
     };
-    if (A.sys.W == 1) return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true>) : go(k_eval_bf16<HMAX, 1, NT, false>);
-    return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true>) : go(k_eval_bf16<HMAX, 2, NT, false>);
+    // in-place hidden layers only where a wave's registers are short (the widest networks)
+    if constexpr (inplace_kernel_bf16(HMAX, NT)) {
+      if (inplace) {
+        if (A.sys.W == 1)
+          return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true, true>) : go(k_eval_bf16<HMAX, 1, NT, false, true>);
+        return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true, true>) : go(k_eval_bf16<HMAX, 2, NT, false, true>);
+      }
+    }
+    if (A.sys.W == 1)
+      return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true, false>) : go(k_eval_bf16<HMAX, 1, NT, false, false>);
+    return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true, false>) : go(k_eval_bf16<HMAX, 2, NT, false, false>);
   });
 }
 
@@ -983,18 +1124,19 @@ hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool 
 }
 
 hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
-                                  bool ldsw, size_t lds, uint32_t bias_off, uint32_t ctx_off, unsigned grid,
-                                  hipStream_t st) {
+                                  bool ldsw, bool inplace, size_t lds, unsigned grid, hipStream_t st) {
   return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
     constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
     auto go = [&](auto kern) {
       hipError_t e = allow_lds(kern, lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, args, first, n_sys,
-                         bias_off, ctx_off);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, args, first, n_sys);
       return hipGetLastError();
     };
-    return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true>) : go(k_eval_multi_bf16<HMAX, NT, false>);
+    if constexpr (inplace_kernel_bf16(HMAX, NT)) {
+      if (inplace) return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true, true>) : go(k_eval_multi_bf16<HMAX, NT, false, true>);
+    }
+    return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true, false>) : go(k_eval_multi_bf16<HMAX, NT, false, false>);
   });
 }
 
