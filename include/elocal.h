@@ -172,6 +172,22 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a,
                           double* eloc, double* logpsi);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): elocal_eval with the same arguments and
+ * results, bit for bit, except that its scratch (what elocal_eval takes as ws) is a fixed
+ * array of ELOCAL_NOALLOC_SCRATCH_MIB MiB in device memory, one per GPU, that the library
+ * holds from the first elocal_create on that GPU until the process ends. The call allocates
+ * nothing. Fails with ELOCAL_E_WORKSPACE when the batch needs more scratch than that
+ * (elocal_workspace_bytes(h, a, B, ELOCAL_OP_EVAL) tells how much; e.g. 60 orbitals with
+ * 1024 samples need about 52 MB). Every call on one GPU shares that GPU's array, and
+ * nothing in it needs to start at zero: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must be serialised by the caller.
+ */
+#define ELOCAL_NOALLOC_SCRATCH_MIB 64
+elocal_status elocal_eval_noalloc(elocal_t h, elocal_stream s, const elocal_ansatz* a,
+                                  const uint64_t* x, int64_t B, double* eloc, double* logpsi);
+
+/*
  * Local energies of several systems in one persistent launch (Methods: the batch of a
  * training step split over independent summands; here systems of different size whose
  * connected lists differ in length by orders of magnitude).

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <utility>
 #include <unordered_map>
+#include <mutex>
 
 #include "../../include/elocal.h"
 #include "elocal_internal.hpp"
@@ -64,6 +65,39 @@ bool is_gfx950(int dev) {
   return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
 }
 
+}  // namespace
+
+// Scratch of elocal_eval_noalloc: a file-scope device array (one copy per GPU, held until the
+// process ends). Host code never passes the array's name to a kernel: each device's address
+// comes from hipGetSymbolAddress, taken once per device in elocal_create with that device
+// current, and is kept in g_scratch.
+static constexpr size_t kNoAllocScratchBytes = (size_t)ELOCAL_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct ScratchTable {
+  std::mutex mu;
+  void* ptr[kMaxDevices] = {};
+  hipError_t err[kMaxDevices] = {};
+  bool done[kMaxDevices] = {};
+};
+ScratchTable& scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+// Looks up this device's scratch address once (the device must be current).
+void setup_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  ScratchTable& t = scratch_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (t.done[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  t.ptr[dev] = (e == hipSuccess) ? p : nullptr;
+  t.err[dev] = e;
+  t.done[dev] = true;
+}
 }  // namespace
 
 struct elocal_ctx {
@@ -477,6 +511,7 @@ elocal_status elocal_create(const double* h1e, const double* eri, int n_orb, int
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
   if (!is_gfx950(dev)) return fail(ELOCAL_E_DEVICE, "device %d is not gfx950", dev);
+  setup_scratch(dev);
   elocal_ctx* h = new elocal_ctx();
   h->dev = dev;
   {
@@ -650,6 +685,31 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
   }
   HIP_TRY(launch_reduce(w.ediag, w.partial, B, p.ips, eloc, st), "reduce launch");
   return ELOCAL_OK;
+}
+
+elocal_status elocal_eval_noalloc(elocal_t h, elocal_stream s, const elocal_ansatz* a, const uint64_t* x,
+                                  int64_t B, double* eloc, double* logpsi) {
+  if (!h) return fail(ELOCAL_E_INVALID, "handle is null");
+  if (elocal_status st = check_device(h)) return st;
+  void* ws = nullptr;
+  {
+    ScratchTable& t = scratch_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (h->dev < 0 || h->dev >= kMaxDevices || !t.done[h->dev])
+      return fail(ELOCAL_E_DEVICE, "no scratch address for device %d", h->dev);
+    if (!t.ptr[h->dev]) return hip_fail(t.err[h->dev], "hipGetSymbolAddress(scratch)");
+    ws = t.ptr[h->dev];
+  }
+  AnsatzGeom G;
+  if (elocal_status e = make_geom(h, a, G)) return e;
+  if (B < 0) return fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B);
+  const size_t need = carve_eval(h, G, plan_eval(h, G, B), B, nullptr).bytes;
+  if (need > kNoAllocScratchBytes)
+    return fail(ELOCAL_E_WORKSPACE,
+                "elocal_eval_noalloc needs %zu bytes of scratch for B=%lld, above its fixed %zu bytes "
+                "(ELOCAL_NOALLOC_SCRATCH_MIB); use elocal_eval with a caller workspace or a smaller batch",
+                need, (long long)B, kNoAllocScratchBytes);
+  return elocal_eval(h, s, a, x, B, ws, kNoAllocScratchBytes, eloc, logpsi);
 }
 
 namespace {

@@ -21,6 +21,7 @@ FP64 = 0
 BF16 = 1      # bfloat16 parameters; two fp16 terms per hidden activation
 BF16X3 = 2    # bfloat16 parameters; three fp16 terms per hidden activation
 OP_CONNECT, OP_EVAL, OP_GRAD = 0, 1, 2
+NOALLOC_SCRATCH_MIB = 64   # ELOCAL_NOALLOC_SCRATCH_MIB of include/elocal.h
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_CONFIG", 3: "E_WORKSPACE", 4: "E_NOMEM", 5: "E_DEVICE",
           6: "E_UNSUPPORTED"}
@@ -61,6 +62,8 @@ def lib():
         L.elocal_connect.argtypes = [vp, vp, vp, i64, vp, sz, vp, vp, vp, vp]
         L.elocal_eval.argtypes = [vp, vp, P(_Ansatz), vp, i64, vp, sz, vp, vp]
         L.elocal_stats.argtypes = [vp, vp, vp, i64, vp]
+        L.elocal_eval_noalloc.argtypes = [vp, vp, P(_Ansatz), vp, i64, vp, vp]
+        L.elocal_eval_noalloc.restype = ctypes.c_int
         L.elocal_grad.argtypes = [vp, vp, P(_Ansatz), vp, vp, vp, i64, vp, sz, vp, vp]
         L.elocal_check_samples.argtypes = [vp, vp, vp, i64, vp, sz, P(i64)]
         L.elocal_last_error.restype = ctypes.c_char_p
@@ -108,7 +111,7 @@ def exported_symbols() -> Sequence[str]:
             "elocal_sector_workspace_bytes", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
             "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_pauli_count", "elocal_pauli_workspace_bytes",
             "elocal_eval_pauli", "elocal_dedup_workspace_bytes", "elocal_eval_dedup", "elocal_sample_workspace_bytes",
-            "elocal_sample"]
+            "elocal_sample", "elocal_eval_noalloc"]
 
 
 def _check(status: int):
@@ -239,6 +242,17 @@ class Hamiltonian:
         ws, nb = self._workspace(OP_EVAL, B, ansatz)
         _check(lib().elocal_eval(self._h, _stream(stream), ansatz.ref(), x.data_ptr(), B, ws.data_ptr(), nb,
                                  eloc.data_ptr(), _ptr(logpsi) if want_logpsi else None))
+        return eloc, logpsi
+
+    def eval_noalloc(self, ansatz: Ansatz, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     logpsi: Optional[torch.Tensor] = None, stream=None):
+        """elocal_eval_noalloc: eval with the library's fixed scratch instead of a workspace
+        (outputs are the caller's; nothing else is allocated)."""
+        x = self._x(x)
+        B = x.shape[0]
+        eloc = out if out is not None else torch.empty((B, 2), dtype=torch.float64, device=x.device)
+        _check(lib().elocal_eval_noalloc(self._h, _stream(stream), ansatz.ref(), x.data_ptr(), B, eloc.data_ptr(),
+                                         _ptr(logpsi)))
         return eloc, logpsi
 
     def grad(self, ansatz: Ansatz, x: torch.Tensor, w: torch.Tensor, eloc: torch.Tensor,
