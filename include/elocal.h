@@ -356,17 +356,37 @@ elocal_status elocal_kernel_timing(elocal_t h, double* total_ms, int64_t* launch
 
 /*
  * Launch shape of the fused local-energy kernel (for the autotuner). A value <= 0
- * restores the built-in choice. ELOCAL_TUNE_GRID: blocks of the persistent grid-stride
- * loop over work items (a block has 16 waves in BF16 mode up to hidden width 128 with
- * two terms per activation, fewer for wider networks or three terms; elocal_eval_multi
- * takes it from its first handle); ELOCAL_TUNE_GROUPS:
- * list-entry groups per work
- * item (64 entries per group in BF16 mode, 16 in FP64 mode). Results do not depend on
- * the launch shape except through the fixed per-item summation order (rounding only).
- * Mutates the handle: do not overlap with other calls on it.
+ * restores the built-in choice. elocal_eval_multi takes the grid, waves and tiles per pass
+ * of its first handle (and each system's groups per item from its own handle).
+ *   ELOCAL_TUNE_GRID:   blocks of the persistent grid-stride loop over work items.
+ *   ELOCAL_TUNE_GROUPS: list-entry groups per work item (64 entries per group in BF16
+ *                       mode, 16 in FP64 mode).
+ *   ELOCAL_TUNE_WAVES:  waves per block of the BF16 kernels (at most what the kernel
+ *                       variant is built for; ELOCAL_INFO_MAX_WAVES tells).
+ *   ELOCAL_TUNE_COLS:   16-row tiles per network pass of the BF16 kernels: 1 or 2 (each
+ *                       weight fragment then feeds twice the rows, in twice the registers,
+ *                       so the variant is built for half the waves). Values no variant
+ *                       provides for the ansatz (2 at width 256 in two-term mode, 1 in
+ *                       three-term mode) fall back to the built-in choice.
+ * Results do not depend on the launch shape except through the fixed per-item summation
+ * order (rounding only). Mutates the handle: do not overlap with other calls on it.
  */
-enum { ELOCAL_TUNE_GRID = 0, ELOCAL_TUNE_GROUPS = 1 };
+enum { ELOCAL_TUNE_GRID = 0, ELOCAL_TUNE_GROUPS = 1, ELOCAL_TUNE_WAVES = 2, ELOCAL_TUNE_COLS = 3 };
 elocal_status elocal_tune(elocal_t h, int param, int64_t value);
+
+/*
+ * The launch shape elocal_eval would use for this handle, ansatz and batch size, after the
+ * tuning above (host computation, no device work; -1 on invalid arguments):
+ * ELOCAL_INFO_GRID blocks, ELOCAL_INFO_GROUPS groups per work item, ELOCAL_INFO_WAVES waves
+ * per block, ELOCAL_INFO_COLS tiles per pass, ELOCAL_INFO_MAX_WAVES the waves per block the
+ * kernel variant is built for, ELOCAL_INFO_ITEMS work items, ELOCAL_INFO_LDS_BYTES LDS per
+ * block.
+ */
+enum {
+  ELOCAL_INFO_GRID = 0, ELOCAL_INFO_GROUPS = 1, ELOCAL_INFO_WAVES = 2, ELOCAL_INFO_COLS = 3,
+  ELOCAL_INFO_MAX_WAVES = 4, ELOCAL_INFO_ITEMS = 5, ELOCAL_INFO_LDS_BYTES = 6
+};
+int64_t elocal_launch_info(elocal_t h, const elocal_ansatz* a, int64_t B, int what);
 
 /* Message for the calling thread's last failure ("" if none). */
 const char* elocal_last_error(void);

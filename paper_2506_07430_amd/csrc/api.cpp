@@ -129,6 +129,8 @@ struct elocal_ctx {
   // launch-shape overrides of the fused kernel (<= 0: built-in)
   int64_t tune_grid = 0;
   int64_t tune_groups = 0;
+  int64_t tune_waves = 0;
+  int64_t tune_cols = 0;
 };
 
 namespace {
@@ -271,6 +273,7 @@ struct EvalPlan {
                     // wave contexts and the input table)
   bool inplace;     // BF16: hidden layers updated in place (see inplace_ok)
   size_t lds;
+  int cols;         // BF16: 16-row tiles per network pass (kernel variant)
   int waves;        // waves per block
   unsigned grid;
 };
@@ -344,14 +347,18 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
   p.n_items = (int64_t)p.ips * B;
   for (int l = 0; l < kMaxLayers; ++l) p.stage.frag[l] = -1;
   if (G.precision == ELOCAL_BF16) {
-    p.waves = eval_waves_bf16(G.hmax, G.nterms);
+    p.cols = eval_cols_default_bf16(G.hmax, G.nterms);
+    if (h->tune_cols > 0 && eval_cols_available_bf16(G.hmax, G.nterms, (int)h->tune_cols)) p.cols = (int)h->tune_cols;
+    p.waves = eval_waves_bf16(G.hmax, G.nterms, p.cols);
+    if (h->tune_waves > 0) p.waves = (int)std::min<int64_t>(h->tune_waves, p.waves);
     p.stage = plan_stage(G, G.hmax, p.waves, G.bbytes);
     p.ldsw = p.stage.any;   // one block per CU owns the CU's LDS
     p.lds = (p.ldsw ? p.stage.wbytes + align256(G.bbytes) : 0) + block_lds_bf16(p.waves);
-    p.inplace = inplace_kernel_bf16(G.hmax, G.nterms) && inplace_ok(G.md);
+    p.inplace = inplace_kernel_bf16(G.hmax, G.nterms) && p.cols == 1 && inplace_ok(G.md);
   } else {
     p.ldsw = false;
     p.lds = 0;
+    p.cols = 1;
     p.waves = 4;
   }
   const int64_t want = (p.n_items + p.waves - 1) / p.waves;
@@ -674,7 +681,8 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
   if (timed) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
   if (G.precision == ELOCAL_BF16) {
     set_lds_args(E, p, G.bbytes);
-    HIP_TRY(launch_eval_bf16(E, G.hmax, G.nterms, p.ldsw, p.inplace, p.lds, p.grid, st), "eval launch");
+    HIP_TRY(launch_eval_bf16(E, G.hmax, G.nterms, p.cols, p.ldsw, p.inplace, p.lds, p.grid, p.waves, st),
+            "eval launch");
   } else {
     HIP_TRY(launch_eval_f64(E, G.hmax, p.grid, st), "eval launch");
   }
@@ -726,6 +734,7 @@ struct MultiPlan {
   int hmax, precision;
   bool ldsw;            // BF16: some system stages weights in LDS
   bool inplace;         // BF16: in-place hidden layers (every system allows them)
+  int cols, waves;      // BF16: tiles per pass and waves per block of the launch
   StagePlan stage[ELOCAL_MAX_SYSTEMS];   // BF16: system s's staged layers
   uint32_t bias_off, ctx_off, lut_off;   // BF16: the LDS layout every system shares
   size_t lds;
@@ -767,7 +776,13 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   std::stable_sort(M.order, M.order + n_sys, [&](int u, int v) { return cost[u] > cost[v]; });
   // BF16: index space of chunks (one item per wave of a block, never two systems in a
   // chunk); FP64: index space of items
-  const int unit = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax, M.G[0].nterms) : 1;
+  // BF16 launch shape: the first handle's tuning, for the widest system's kernel
+  M.cols = eval_cols_default_bf16(M.hmax, M.G[0].nterms);
+  if (hs[0]->tune_cols > 0 && eval_cols_available_bf16(M.hmax, M.G[0].nterms, (int)hs[0]->tune_cols))
+    M.cols = (int)hs[0]->tune_cols;
+  M.waves = eval_waves_bf16(M.hmax, M.G[0].nterms, M.cols);
+  if (hs[0]->tune_waves > 0) M.waves = (int)std::min<int64_t>(hs[0]->tune_waves, M.waves);
+  const int unit = (M.precision == ELOCAL_BF16) ? M.waves : 1;
   M.first[0] = 0;
   for (int i = 0; i < n_sys; ++i) M.first[i + 1] = M.first[i] + (M.p[M.order[i]].n_items + unit - 1) / unit;
   M.ldsw = M.inplace = false;
@@ -775,10 +790,10 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   M.lds = 0;
   if (M.precision == ELOCAL_BF16) {
     // one LDS layout for all systems, sized for the kernel's width class and wave count
-    const int waves = eval_waves_bf16(M.hmax, M.G[0].nterms);
+    const int waves = M.waves;
     size_t wmax = 0, bmax = 0;
     for (int s = 0; s < n_sys; ++s) bmax = std::max(bmax, align256(M.G[s].bbytes));
-    M.inplace = inplace_kernel_bf16(M.hmax, M.G[0].nterms);
+    M.inplace = inplace_kernel_bf16(M.hmax, M.G[0].nterms) && M.cols == 1;
     for (int s = 0; s < n_sys; ++s) {
       M.stage[s] = plan_stage(M.G[s], M.hmax, waves, bmax);
       M.ldsw = M.ldsw || M.stage[s].any;
@@ -797,7 +812,7 @@ elocal_status plan_multi(int n_sys, const elocal_t* hs, const elocal_ansatz* con
   M.first_off = off;
   off = align256(off + sizeof(int64_t) * (n_sys + 1));
   M.bytes = off;
-  const int waves = (M.precision == ELOCAL_BF16) ? eval_waves_bf16(M.hmax, M.G[0].nterms) : 4;
+  const int waves = (M.precision == ELOCAL_BF16) ? M.waves : 4;
   const int64_t want = (M.precision == ELOCAL_BF16) ? M.first[n_sys] : (M.first[n_sys] + 3) / 4;
   M.grid = (unsigned)std::max<int64_t>(1, std::min(want, grid_cap(hs[0], waves)));
   return ELOCAL_OK;
@@ -867,8 +882,8 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s, 
   if (M.first[n_sys] > 0) {
     if (timed) HIP_TRY(hipEventRecord(h0->ev_start[slot], st), "timing event");
     if (M.precision == ELOCAL_BF16)
-      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.G[0].nterms, M.ldsw, M.inplace, M.lds,
-                                     M.grid, st),
+      HIP_TRY(launch_eval_multi_bf16(d_args, d_first, n_sys, M.hmax, M.G[0].nterms, M.cols, M.ldsw, M.inplace, M.lds,
+                                     M.grid, M.waves, st),
               "multi eval launch");
     else
       HIP_TRY(launch_eval_multi_f64(d_args, d_first, n_sys, M.hmax, M.grid, st), "multi eval launch");
@@ -1053,7 +1068,7 @@ elocal_status elocal_eval_pauli(elocal_t h, elocal_stream s, const elocal_ansatz
   const bool timed = h->timing && p.n_items > 0;
   const int slot = (int)(h->ring_pos % elocal_ctx::kRing);
   if (timed) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
-  HIP_TRY(launch_eval_pauli_bf16(E, G.hmax, G.nterms, p.ldsw, p.lds, p.grid, st), "Pauli eval launch");
+  HIP_TRY(launch_eval_pauli_bf16(E, G.hmax, G.nterms, p.ldsw, p.lds, p.grid, p.waves, st), "Pauli eval launch");
   if (timed) {
     HIP_TRY(hipEventRecord(h->ev_stop[slot], st), "timing event");
     h->ring_pos++;
@@ -1421,8 +1436,30 @@ elocal_status elocal_tune(elocal_t h, int param, int64_t value) {
   switch (param) {
     case ELOCAL_TUNE_GRID: h->tune_grid = value; return ELOCAL_OK;
     case ELOCAL_TUNE_GROUPS: h->tune_groups = value; return ELOCAL_OK;
+    case ELOCAL_TUNE_WAVES: h->tune_waves = value; return ELOCAL_OK;
+    case ELOCAL_TUNE_COLS: h->tune_cols = value; return ELOCAL_OK;
   }
   return fail(ELOCAL_E_INVALID, "unknown tuning parameter %d", param);
+}
+
+int64_t elocal_launch_info(elocal_t h, const elocal_ansatz* a, int64_t B, int what) {
+  if (!h) { fail(ELOCAL_E_INVALID, "handle is null"); return -1; }
+  if (B < 0) { fail(ELOCAL_E_INVALID, "B=%lld is negative", (long long)B); return -1; }
+  AnsatzGeom G;
+  if (make_geom(h, a, G) != ELOCAL_OK) return -1;
+  const EvalPlan p = plan_eval(h, G, B);
+  switch (what) {
+    case ELOCAL_INFO_GRID: return p.grid;
+    case ELOCAL_INFO_GROUPS: return p.tpi;
+    case ELOCAL_INFO_WAVES: return p.waves;
+    case ELOCAL_INFO_COLS: return p.cols;
+    case ELOCAL_INFO_MAX_WAVES:
+      return G.precision == ELOCAL_BF16 ? eval_waves_bf16(G.hmax, G.nterms, p.cols) : p.waves;
+    case ELOCAL_INFO_ITEMS: return p.n_items;
+    case ELOCAL_INFO_LDS_BYTES: return (int64_t)p.lds;
+  }
+  fail(ELOCAL_E_INVALID, "unknown launch-info query %d", what);
+  return -1;
 }
 
 elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* x, int64_t B, void* ws,

@@ -68,18 +68,23 @@ hipError_t launch_check(const SysDev& S, const uint64_t* x, int64_t B, unsigned 
 hipError_t launch_pack_bf16(const MadeDev& M, const ThetaLayout& T, const uint16_t* theta,
                             void* frag, float* bias, hipStream_t st);
 hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t st);
-hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, bool inplace,
-                            size_t lds_bytes, unsigned grid, hipStream_t st);
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, int cols, bool lds_weights, bool inplace,
+                            size_t lds_bytes, unsigned grid, int waves, hipStream_t st);
 
-// Shape of the BF16 fused kernels (single and multi-system), one block per CU. With two
-// fp16 terms per activation a pass of the network takes one 16-row tile, so that a wave
-// fits in 128 registers up to width 128 (16 waves per block, four per SIMD) and in 256 at
-// width 256 (8 waves, two per SIMD): the VALU and MFMA work of different waves on a SIMD
-// overlap the more waves share it. Three terms take two tiles per pass (8 waves up to
-// hmax * nterms = 256, else 4).
-constexpr int eval_cols_bf16(int hmax, int nterms) { return nterms == 2 ? 1 : 2; }
-constexpr int eval_waves_bf16(int hmax, int nterms) {
-  return eval_cols_bf16(hmax, nterms) == 1 ? (hmax <= 128 ? 16 : 8) : hmax * nterms <= 256 ? 8 : 4;
+// Shape of the BF16 fused kernels (single and multi-system), one block per CU. A network
+// pass takes NC 16-row tiles. With two fp16 terms per activation the built-in NC is 1, so
+// that a wave fits in 128 registers up to width 128 (16 waves per block, four per SIMD)
+// and in 256 at width 256 (8 waves, two per SIMD): the VALU and MFMA work of different
+// waves on a SIMD overlap the more waves share it. NC = 2 (each weight fragment feeds
+// twice the rows, in twice the registers: 8 waves per block) is also built up to width
+// 128, for the autotuner. Three terms take NC = 2 (8 waves up to hmax * nterms = 256,
+// else 4). A launch may use fewer waves per block than a variant is built for.
+constexpr int eval_cols_default_bf16(int hmax, int nterms) { return nterms == 2 ? 1 : 2; }
+constexpr bool eval_cols_available_bf16(int hmax, int nterms, int nc) {
+  return nc == eval_cols_default_bf16(hmax, nterms) || (nterms == 2 && nc == 2 && hmax <= 128);
+}
+constexpr int eval_waves_bf16(int hmax, int nterms, int nc) {
+  return nc == 1 ? (hmax <= 128 ? 16 : 8) : hmax * nterms <= 256 ? 8 : 4;
 }
 constexpr int kMaxEvalWavesBF16 = 16;
 // Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists and
@@ -100,16 +105,17 @@ constexpr size_t block_lds_bf16(int waves) { return (size_t)waves * kWaveCtxByte
 // o-block pair j reads no k-block beyond j + 1.
 constexpr bool inplace_kernel_bf16(int hmax, int nterms) { return hmax >= kLdsPartialWidth && nterms == 2; }
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system
-// s owns chunks [first[s], first[s+1]) of eval_waves_bf16(hmax, nterms) work items each (LDS layout as
+// s owns chunks [first[s], first[s+1]) of `waves` work items each (LDS layout as
 // for one system, with the bias, context and table offsets of args[0] for all). FP64:
 // system s owns work items [first[s], first[s+1]).
 hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool lds_weights, size_t lds_bytes,
-                                  unsigned grid, hipStream_t st);
+                                  unsigned grid, int waves, hipStream_t st);
 // Pauli route, diagonal (identity-flip) group: ediag[b] = sum_k c_k (-1)^|z_k & x_b|.
 hipError_t launch_pauli_diag(const uint64_t* x, int64_t B, const uint32_t* off, const uint64_t* z,
                              const double* coef, double* ediag, hipStream_t st);
 hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
-                                  bool ldsw, bool inplace, size_t lds, unsigned grid, hipStream_t st);
+                                  int cols, bool ldsw, bool inplace, size_t lds, unsigned grid, int waves,
+                                  hipStream_t st);
 hipError_t launch_eval_multi_f64(const EvalArgs* args, const int64_t* first, int n_sys, int hmax,
                                  unsigned grid, hipStream_t st);
 // Host record (bytes a multiple of 4) -> device memory, in stream order.

@@ -24,6 +24,7 @@
 // significant bits; 2^-25 absolute for the smallest values), where two bfloat16 terms
 // would leave 2^-16 |a|. Accumulation is FP32; the ratio exp(dA + i dphi), the matrix
 // element and every sum are FP64.
+#include <algorithm>
 #include <type_traits>
 
 #include "elocal_internal.hpp"
@@ -774,11 +775,11 @@ __device__ __attribute__((noinline)) double2 ratio_term(double hv, float zp, dou
 // network runs in 4 / NC passes of NC 16-row tiles over the 64 entries; every lane then
 // forms H exp(dA + i dphi) in FP64 for its own entry. The item's partial sum (fixed
 // order) goes to P.partial[item].
-template <int HMAX, int NW, int NT, bool INPLACE = false, class Gen = ScGen>
+template <int HMAX, int NW, int NT, bool INPLACE = false, class Gen = ScGen,
+          int NC = eval_cols_default_bf16(HMAX, NT)>
 __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t* lds, const unsigned char* smem,
                                                const float* __restrict__ bias, const uint64_t* xlut,
                                                WaveCtxBF16& wc, int64_t item, SampleState<NW>& st, int lane) {
-  constexpr int NC = eval_cols_bf16(HMAX, NT);
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
   const int g = lane >> 4, r16 = lane & 15;
@@ -940,9 +941,9 @@ __device__ __forceinline__ uint64_t* fill_xlut(unsigned char* smem, uint32_t lut
 
 // One system; a persistent grid strides over the work items, one wave per item. With
 // LDSW the layers the host placed in LDS (P.lds_frag) and the biases are first staged.
-template <int HMAX, int NW, int NT, bool LDSW, bool INPLACE>
-__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16(EvalArgs P) {
-  constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
+template <int HMAX, int NW, int NT, bool LDSW, bool INPLACE, int NC>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT, NC), 1) k_eval_bf16(EvalArgs P) {
+  const int kEvalWaves = blockDim.x >> 6;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   const float* bias = (const float*)P.made.bias;
@@ -957,14 +958,16 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_bf16
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * kEvalWaves + wid; item < P.n_items;
        item += (int64_t)gridDim.x * kEvalWaves)
-    eval_item_bf16<HMAX, NW, NT, INPLACE>(P, LDSW ? P.lds_frag : nullptr, smem, bias, xlut, wc, item, st, lane);
+    eval_item_bf16<HMAX, NW, NT, INPLACE, ScGen, NC>(P, LDSW ? P.lds_frag : nullptr, smem, bias, xlut, wc, item, st,
+                                                    lane);
 }
 
 // Pauli-string route: the fused kernel over the unique flip masks of every sample (one
 // word per determinant: n <= 32).
 template <int HMAX, int NT, bool LDSW>
-__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_pauli_bf16(EvalArgs P) {
-  constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT, eval_cols_default_bf16(HMAX, NT)), 1)
+    k_eval_pauli_bf16(EvalArgs P) {
+  const int kEvalWaves = blockDim.x >> 6;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   const float* bias = (const float*)P.made.bias;
@@ -990,10 +993,10 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1) k_eval_paul
 // restages the weights whenever its next chunk belongs to another system (every system's
 // staged layers, biases, wave contexts and input table share one LDS layout: the offsets
 // of system 0's arguments).
-template <int HMAX, int NT, bool LDSW, bool INPLACE>
-__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
+template <int HMAX, int NT, bool LDSW, bool INPLACE, int NC>
+__global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT, NC), 1)
     k_eval_multi_bf16(const EvalArgs* __restrict__ args, const int64_t* __restrict__ first, int n_sys) {
-  constexpr int kEvalWaves = eval_waves_bf16(HMAX, NT);
+  const int kEvalWaves = blockDim.x >> 6;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int lane = threadIdx.x & 63, wid = sgpr(threadIdx.x >> 6);
   const uint32_t bias_off = args[0].lds_bias_off, ctx_off = args[0].lds_ctx_off;
@@ -1026,8 +1029,8 @@ __global__ void __launch_bounds__(64 * eval_waves_bf16(HMAX, NT), 1)
     const int64_t local = (chunk - first[s]) * kEvalWaves + wid;
     if (local < P.n_items) {
       const int32_t* lds = LDSW ? P.lds_frag : nullptr;
-      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT, INPLACE>(P, lds, smem, bias, xlut, wc, local, st1, lane);
-      else eval_item_bf16<HMAX, 2, NT, INPLACE>(P, lds, smem, bias, xlut, wc, local, st2, lane);
+      if (P.sys.W == 1) eval_item_bf16<HMAX, 1, NT, INPLACE, ScGen, NC>(P, lds, smem, bias, xlut, wc, local, st1, lane);
+      else eval_item_bf16<HMAX, 2, NT, INPLACE, ScGen, NC>(P, lds, smem, bias, xlut, wc, local, st2, lane);
     }
   }
 }
@@ -1082,33 +1085,48 @@ hipError_t launch_rows_bf16(const RowsArgs& A, int hmax, int nterms, hipStream_t
   });
 }
 
-hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, bool inplace, size_t lds,
-                            unsigned grid, hipStream_t st) {
+// Calls f(integral_constant<NC>) for the tiles per pass `cols` if that variant is built for
+// (HMAX, NT), else for the built-in one.
+template <int HMAX, int NT, class F>
+static hipError_t dispatch_cols(int cols, F&& f) {
+  using std::integral_constant;
+  if constexpr (eval_cols_available_bf16(HMAX, NT, 2) && eval_cols_default_bf16(HMAX, NT) != 2) {
+    if (cols == 2) return f(integral_constant<int, 2>{});
+  }
+  return f(integral_constant<int, eval_cols_default_bf16(HMAX, NT)>{});
+}
+
+hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, int cols, bool ldsw, bool inplace, size_t lds,
+                            unsigned grid, int waves, hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
   return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
     constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
-    auto go = [&](auto kern) {
-      hipError_t e = allow_lds(kern, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, A);
-      return hipGetLastError();
-    };
-    // in-place hidden layers only where a wave's registers are short (the widest networks)
-    if constexpr (inplace_kernel_bf16(HMAX, NT)) {
-      if (inplace) {
-        if (A.sys.W == 1)
-          return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true, true>) : go(k_eval_bf16<HMAX, 1, NT, false, true>);
-        return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true, true>) : go(k_eval_bf16<HMAX, 2, NT, false, true>);
+    return dispatch_cols<HMAX, NT>(cols, [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        const int w = std::max(1, std::min(waves, eval_waves_bf16(HMAX, NT, NC)));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), lds, st, A);
+        return hipGetLastError();
+      };
+      // in-place hidden layers only where a wave's registers are short (the widest networks)
+      if constexpr (inplace_kernel_bf16(HMAX, NT) && NC == 1) {
+        if (inplace) {
+          if (A.sys.W == 1)
+            return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true, true, NC>) : go(k_eval_bf16<HMAX, 1, NT, false, true, NC>);
+          return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true, true, NC>) : go(k_eval_bf16<HMAX, 2, NT, false, true, NC>);
+        }
       }
-    }
-    if (A.sys.W == 1)
-      return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true, false>) : go(k_eval_bf16<HMAX, 1, NT, false, false>);
-    return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true, false>) : go(k_eval_bf16<HMAX, 2, NT, false, false>);
+      if (A.sys.W == 1)
+        return ldsw ? go(k_eval_bf16<HMAX, 1, NT, true, false, NC>) : go(k_eval_bf16<HMAX, 1, NT, false, false, NC>);
+      return ldsw ? go(k_eval_bf16<HMAX, 2, NT, true, false, NC>) : go(k_eval_bf16<HMAX, 2, NT, false, false, NC>);
+    });
   });
 }
 
 hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool ldsw, size_t lds, unsigned grid,
-                                  hipStream_t st) {
+                                  int waves, hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
   if (A.sys.W != 1) return hipErrorInvalidValue;
   return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
@@ -1116,7 +1134,8 @@ hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool 
     auto go = [&](auto kern) {
       hipError_t e = allow_lds(kern, lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, A);
+      const int w = std::max(1, std::min(waves, eval_waves_bf16(HMAX, NT, eval_cols_default_bf16(HMAX, NT))));
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), lds, st, A);
       return hipGetLastError();
     };
     return ldsw ? go(k_eval_pauli_bf16<HMAX, NT, true>) : go(k_eval_pauli_bf16<HMAX, NT, false>);
@@ -1124,19 +1143,25 @@ hipError_t launch_eval_pauli_bf16(const EvalArgs& A, int hmax, int nterms, bool 
 }
 
 hipError_t launch_eval_multi_bf16(const EvalArgs* args, const int64_t* first, int n_sys, int hmax, int nterms,
-                                  bool ldsw, bool inplace, size_t lds, unsigned grid, hipStream_t st) {
+                                  int cols, bool ldsw, bool inplace, size_t lds, unsigned grid, int waves,
+                                  hipStream_t st) {
   return dispatch_shape(hmax, nterms, [&](auto h, auto t) {
     constexpr int HMAX = decltype(h)::value, NT = decltype(t)::value;
-    auto go = [&](auto kern) {
-      hipError_t e = allow_lds(kern, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * eval_waves_bf16(HMAX, NT)), lds, st, args, first, n_sys);
-      return hipGetLastError();
-    };
-    if constexpr (inplace_kernel_bf16(HMAX, NT)) {
-      if (inplace) return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true, true>) : go(k_eval_multi_bf16<HMAX, NT, false, true>);
-    }
-    return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true, false>) : go(k_eval_multi_bf16<HMAX, NT, false, false>);
+    return dispatch_cols<HMAX, NT>(cols, [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        const int w = std::max(1, std::min(waves, eval_waves_bf16(HMAX, NT, NC)));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), lds, st, args, first, n_sys);
+        return hipGetLastError();
+      };
+      if constexpr (inplace_kernel_bf16(HMAX, NT) && NC == 1) {
+        if (inplace)
+          return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true, true, NC>) : go(k_eval_multi_bf16<HMAX, NT, false, true, NC>);
+      }
+      return ldsw ? go(k_eval_multi_bf16<HMAX, NT, true, false, NC>) : go(k_eval_multi_bf16<HMAX, NT, false, false, NC>);
+    });
   });
 }
 

@@ -70,6 +70,8 @@ def lib():
         L.elocal_timing_enable.argtypes = [vp, i32]
         L.elocal_kernel_timing.argtypes = [vp, P(ctypes.c_double), P(i64), i32]
         L.elocal_tune.argtypes = [vp, i32, i64]
+        L.elocal_launch_info.argtypes = [vp, P(_Ansatz), i64, i32]
+        L.elocal_launch_info.restype = i64
         L.elocal_sample_workspace_bytes.argtypes = [vp, P(_Ansatz), i64]
         L.elocal_sample_workspace_bytes.restype = sz
         L.elocal_sample.argtypes = [vp, vp, P(_Ansatz), i64, ctypes.c_uint64, i64, vp, sz, vp, vp, P(i64)]
@@ -111,7 +113,7 @@ def exported_symbols() -> Sequence[str]:
             "elocal_sector_workspace_bytes", "elocal_sector_basis", "elocal_sector_apply", "elocal_kpm_moments",
             "elocal_kpm_line_shape", "elocal_pauli_build", "elocal_pauli_count", "elocal_pauli_workspace_bytes",
             "elocal_eval_pauli", "elocal_dedup_workspace_bytes", "elocal_eval_dedup", "elocal_sample_workspace_bytes",
-            "elocal_sample", "elocal_eval_noalloc"]
+            "elocal_sample", "elocal_eval_noalloc", "elocal_launch_info"]
 
 
 def _check(status: int):
@@ -282,10 +284,22 @@ class Hamiltonian:
         _check(lib().elocal_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(reset)))
         return ms.value, int(n.value)
 
-    def tune(self, grid: int = 0, groups: int = 0):
-        """Launch shape of the fused kernel (0 = built-in)."""
-        _check(lib().elocal_tune(self._h, 0, int(grid)))
-        _check(lib().elocal_tune(self._h, 1, int(groups)))
+    def tune(self, grid: int = 0, groups: int = 0, waves: int = 0, cols: int = 0):
+        """Launch shape of the fused kernel (0 = built-in): blocks, entry groups per work item,
+        waves per block, 16-row tiles per network pass."""
+        for param, value in enumerate((grid, groups, waves, cols)):
+            _check(lib().elocal_tune(self._h, param, int(value)))
+
+    def launch_info(self, ansatz: Ansatz, B: int) -> dict:
+        """The launch shape elocal_eval would use for this ansatz and batch size."""
+        keys = ("grid", "groups", "waves", "cols", "max_waves", "items", "lds_bytes")
+        out = {}
+        for i, k in enumerate(keys):
+            v = lib().elocal_launch_info(self._h, ansatz.ref(), int(B), i)
+            if v < 0:
+                raise ElocalError(1, lib().elocal_last_error().decode())
+            out[k] = int(v)
+        return out
 
     # ------------------------------------------------------------------ sampling
     def sample(self, ansatz: Ansatz, n_samples: int, seed: int, max_unique: int = 1 << 20, stream=None):

@@ -79,3 +79,27 @@ def _has_gpu():
         return torch.cuda.device_count() > 0
     except Exception:
         return False
+
+
+def test_autotune_search_and_cache_on_host(tmp_path):
+    """The coordinate search and the JSON cache (no GPU): the search starts at the built-in
+    shape, walks each dimension with the others held at the best so far, stops at the
+    budget; the cache round-trips and keeps other entries."""
+    from paper_2506_07430_amd import autotune
+    cost = {"cols": {0: 3.0, 1: 3.0, 2: 2.0}, "waves": {0: 0.0, 8: 1.0}, "groups": {0: 0.5, 4: 0.0, 16: 0.7},
+            "grid": {0: 0.2, 512: 0.0}}
+
+    def timed(shape):
+        return 10.0 + sum(cost[k][shape[k]] for k in cost)
+
+    table = autotune._search({"cols": [0, 1, 2], "waves": [0, 8], "groups": [0, 4, 16], "grid": [0, 512]}, timed, 1e9)
+    best = min(table, key=lambda r: r["ms"])
+    assert table[0]["shape"] == {"grid": 0, "groups": 0, "waves": 0, "cols": 0}
+    assert best["shape"] == {"grid": 512, "groups": 4, "waves": 0, "cols": 2}
+    assert len({tuple(sorted(r["shape"].items())) for r in table}) == len(table)
+    short = autotune._search({"cols": [0, 1, 2], "waves": [0, 8]}, timed, 0.0)
+    assert len(short) == 1
+    path = str(tmp_path / "c.json")
+    autotune.store_cache("a", {"shape": {"grid": 1}}, path)
+    autotune.store_cache("b", {"shape": {"grid": 2}}, path)
+    assert autotune.load_cache(path) == {"a": {"shape": {"grid": 1}}, "b": {"shape": {"grid": 2}}}
