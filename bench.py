@@ -387,11 +387,25 @@ def main():
             t0 = time.perf_counter()
             xs_, cs_ = cham.sample(ca64, args.sampler_draws, 2026)
             t_s = time.perf_counter() - t0
+            # the same call at 10^12 draws on the 8-orbital ansatz: the cost follows the distinct
+            # prefixes (4,900 leaves), not the draws
+            sp = synth.make_problem(0)
+            sham = elocal.Hamiltonian(sp.h1e, sp.eri, sp.system.n, sp.system.n_alpha, sp.system.n_beta)
+            sans = elocal.Ansatz(sp.system.widths, torch.tensor(sp.theta, dtype=torch.float64, device=dev), elocal.FP64)
+            sham.sample(sans, 1000, 1)
+            big = {}
+            for nd in (10 ** 5, 10 ** 12):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xb, _ = sham.sample(sans, nd, 2026)
+                big[nd] = (time.perf_counter() - t0, int(xb.shape[0]))
             out["sampler"] = {"workload": "24 orbitals, 12a+12b, FP64 ansatz 128x2", "draws": args.sampler_draws,
                               "distinct": int(xs_.shape[0]), "seconds": t_s,
                               "draws_per_s": args.sampler_draws / t_s, "orbital_steps": cp.system.n,
-                              "note": "synchronous call (the tree size is read back per orbital)"}
-            del xs_, cs_
+                              "n8_1e5_draws_s": big[10 ** 5][0], "n8_1e12_draws_s": big[10 ** 12][0],
+                              "n8_distinct": big[10 ** 12][1],
+                              "note": "multinomial split per prefix (binomial chain); one host sync per call"}
+            del xs_, cs_, sham
 
         # --- the paper's Pauli-string route on the same ansatz and samples: every unique flip
         # of the Jordan--Wigner strings goes through the ansatz (vs the C connected ones)

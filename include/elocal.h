@@ -212,18 +212,21 @@ elocal_status elocal_eval_multi(int n_sys, const elocal_t* hs, elocal_stream s,
 /*
  * Batch autoregressive sampling (Results, parallel sampling: the BAS tree of unique
  * prefixes with multiplicities, pruned at every orbital, under the number-conserving
- * conditionals). Draws n_samples in [1, 2^32) determinants from |Psi|^2 and returns them as
+ * conditionals). Draws n_samples in [1, 2^53] determinants from |Psi|^2 and returns them as
  * *n_unique distinct determinants x_out [*n_unique][W] with counts counts_out [*n_unique]
- * (device buffers of max_unique entries), in tree order (prefix, then state 0 = empty,
- * 1 = alpha, 2 = beta, 3 = both). At orbital k every prefix i with weight w splits it by w
- * independent categorical draws: draw j uses u = (first 53 bits of words 0-1 of
- * Philox4x32-10 at counter (j, i, k, 0), key (seed low, seed high)) * 2^-53 and takes the
- * first reachable state whose running probability sum exceeds u (else the last reachable
- * one). The ansatz is evaluated in FP64 (ELOCAL_FP64 only), so the draws are reproducible.
- * Synchronous (the tree size is read back at every orbital); ELOCAL_E_WORKSPACE if some
- * orbital has more than max_unique distinct prefixes. Workspace:
- * elocal_sample_workspace_bytes. Cost: n orbital steps, each an ansatz pass over the
- * distinct prefixes and n_samples categorical draws.
+ * (device buffers of max_unique entries, max_unique < 2^32), in tree order (prefix, then
+ * state 0 = empty, 1 = alpha, 2 = beta, 3 = both). At orbital k every prefix i splits its
+ * weight w by one multinomial draw, a chain of binomials over its reachable states in
+ * ascending order: state s gets Binomial(w left, p_s / (p_s + later reachable p)), the last
+ * reachable state the rest. A binomial with n p < 10 (p <= 1/2, else n minus the variate
+ * for 1 - p) is drawn by inversion from 0, otherwise by BTRD (W. Hormann, J. Stat. Comput.
+ * Simul. 46, 1993); attempt t of state s uses the two 53-bit uniforms of Philox4x32-10 at
+ * counter (t, i, k, s), key (seed low, seed high): words (0,1) and (2,3), times 2^-53. The
+ * ansatz is evaluated in FP64 (ELOCAL_FP64 only), so the tree is reproducible. The cost of
+ * a step depends on the number of distinct prefixes only, not on n_samples. Synchronous
+ * (once, at the end: the steps keep the prefix counts on the device); ELOCAL_E_WORKSPACE
+ * if some orbital has more than max_unique distinct prefixes. Workspace:
+ * elocal_sample_workspace_bytes.
  */
 size_t elocal_sample_workspace_bytes(elocal_t h, const elocal_ansatz* a, int64_t max_unique);
 elocal_status elocal_sample(elocal_t h, elocal_stream s, const elocal_ansatz* a, int64_t n_samples,

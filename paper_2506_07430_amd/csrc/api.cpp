@@ -1090,7 +1090,8 @@ struct SampleWs {
   int64_t* counts;
   int64_t* off;
   int64_t* btot;
-  int64_t* total;
+  int64_t* ucount;   // [2] prefix counts of the current and the next step (device)
+  int64_t* overflow;
   size_t bytes;
 };
 
@@ -1108,14 +1109,10 @@ SampleWs carve_sample(const elocal_ctx* h, const AnsatzGeom& G, int64_t cap, voi
   w.counts = c.take<int64_t>(4 * C);
   w.off = c.take<int64_t>(C);
   w.btot = c.take<int64_t>((C + 1023) / 1024);
-  w.total = c.take<int64_t>(1);
+  w.ucount = c.take<int64_t>(2);
+  w.overflow = c.take<int64_t>(1);
   w.bytes = c.off;
   return w;
-}
-
-__global__ void k_sample_root(uint64_t* pre, int64_t* w, int W, int64_t n_samples) {
-  if (threadIdx.x < (unsigned)W) pre[threadIdx.x] = 0ull;
-  if (threadIdx.x == 0) w[0] = n_samples;
 }
 
 }  // namespace
@@ -1134,9 +1131,9 @@ elocal_status elocal_sample(elocal_t h, elocal_stream s, const elocal_ansatz* a,
   AnsatzGeom G;
   if (elocal_status e = make_geom(h, a, G)) return e;
   if (G.precision != ELOCAL_FP64) return fail(ELOCAL_E_UNSUPPORTED, "the sampler evaluates the ansatz in FP64 only");
-  if (n_samples < 1 || n_samples > 0xFFFFFFFFll)
-    return fail(ELOCAL_E_INVALID, "n_samples=%lld outside [1, 2^32 - 1]", (long long)n_samples);
-  if (max_unique < 1) return fail(ELOCAL_E_INVALID, "max_unique < 1");
+  if (n_samples < 1 || n_samples > (1ll << 53))
+    return fail(ELOCAL_E_INVALID, "n_samples=%lld outside [1, 2^53]", (long long)n_samples);
+  if (max_unique < 1 || max_unique > 0xFFFFFFFFll) return fail(ELOCAL_E_INVALID, "max_unique outside [1, 2^32 - 1]");
   if (!a->theta || !ws || !x_out || !counts_out || !n_unique) return fail(ELOCAL_E_INVALID, "null pointer argument");
   const SampleWs need = carve_sample(h, G, max_unique, nullptr);
   if (ws_bytes < need.bytes) return fail(ELOCAL_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need.bytes);
@@ -1147,29 +1144,26 @@ elocal_status elocal_sample(elocal_t h, elocal_stream s, const elocal_ansatz* a,
   M.wfrag = w.frag;
   M.bias = w.bias;
   HIP_TRY(launch_pack_f64(M, G.T, (const double*)a->theta, w.frag, (double*)w.bias, st), "pack launch");
-  hipLaunchKernelGGL(k_sample_root, dim3(1), dim3(64), 0, st, w.pre[0], w.w[0], h->sys.W, n_samples);
-  HIP_TRY(hipGetLastError(), "root launch");
-  int64_t U = 1;
+  HIP_TRY(launch_bas_root(w.pre[0], w.w[0], h->sys.W, n_samples, &w.ucount[0], w.overflow, st), "root launch");
+  // every step's launch sizes follow max_unique, the prefix counts stay on the device; the
+  // last step writes the leaves straight into the caller's buffers
   int cur = 0;
-  for (int k = 0; k < h->sys.n; ++k) {
-    HIP_TRY(launch_bas_step(h->sys, M, G.hmax, w.pre[cur], w.w[cur], U, k, seed, w.probs, w.counts, w.off, w.btot,
-                            w.total, w.pre[1 - cur], w.w[1 - cur], max_unique, n_samples, st),
+  const int n = h->sys.n;
+  for (int k = 0; k < n; ++k) {
+    const bool last = k + 1 == n;
+    HIP_TRY(launch_bas_step(h->sys, M, G.hmax, w.pre[cur], w.w[cur], &w.ucount[cur], &w.ucount[1 - cur], w.overflow,
+                            k, seed, w.probs, w.counts, w.off, w.btot, last ? x_out : w.pre[1 - cur],
+                            last ? counts_out : w.w[1 - cur], max_unique, st),
             "sampling step launch");
-    int64_t next = 0;
-    HIP_TRY(hipMemcpyAsync(&next, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, st), "count copy");
-    HIP_TRY(hipStreamSynchronize(st), "sampling step sync");
-    if (next > max_unique)
-      return fail(ELOCAL_E_WORKSPACE, "%lld distinct prefixes at orbital %d exceed max_unique=%lld", (long long)next,
-                  k, (long long)max_unique);
-    U = next;
     cur = 1 - cur;
   }
-  HIP_TRY(hipMemcpyAsync(x_out, w.pre[cur], (size_t)U * h->sys.W * sizeof(uint64_t), hipMemcpyDeviceToDevice, st),
-          "sample copy");
-  HIP_TRY(hipMemcpyAsync(counts_out, w.w[cur], (size_t)U * sizeof(int64_t), hipMemcpyDeviceToDevice, st),
-          "count copy");
+  int64_t hv[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&hv[0], &w.ucount[cur], sizeof(int64_t), hipMemcpyDeviceToHost, st), "count copy");
+  HIP_TRY(hipMemcpyAsync(&hv[1], w.overflow, sizeof(int64_t), hipMemcpyDeviceToHost, st), "count copy");
   HIP_TRY(hipStreamSynchronize(st), "sampling sync");
-  *n_unique = U;
+  if (hv[1]) return fail(ELOCAL_E_WORKSPACE, "more than max_unique=%lld distinct prefixes at some orbital",
+                         (long long)max_unique);
+  *n_unique = hv[0];
   return ELOCAL_OK;
 }
 

@@ -152,15 +152,19 @@ hipError_t launch_dd_assemble(const uint64_t* xp, const double* hval, int64_t B,
                               const uint32_t* ids, uint64_t mask, const double* logpsi_u, double* eloc,
                               double* logpsi_out, int64_t* counters, hipStream_t st);
 
-// Batch autoregressive sampling: conditional of orbital k for U prefixes (FP64 ansatz),
-// and one full tree step (conditionals, Philox draws, scan, children). `total` receives
-// the number of children (entries beyond `cap` are not written). `ndraws` is the number of
-// draws of the whole tree (every step's weights sum to it).
-hipError_t launch_bas_probs(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, int64_t U, int k,
-                            double* probs, hipStream_t st);
+// Batch autoregressive sampling: conditional of orbital k for the first min(*Ud, cap)
+// prefixes (FP64 ansatz), and one full tree step (conditionals, multinomial split of every
+// prefix's weight, scan, children). The prefix count of the step is *ucur (device); the
+// step writes the children's count to *unext and raises *overflow when it exceeds `cap`
+// (children beyond it are not written). Launch sizes depend on `cap` only, so the steps
+// need no host synchronisation.
+hipError_t launch_bas_probs(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* Ud,
+                            int64_t cap, int k, double* probs, hipStream_t st);
 hipError_t launch_bas_step(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* w,
-                           int64_t U, int k, uint64_t seed, double* probs, int64_t* counts, int64_t* off,
-                           int64_t* btot, int64_t* total, uint64_t* child, int64_t* cw, int64_t cap, int64_t ndraws,
+                           const int64_t* ucur, int64_t* unext, int64_t* overflow, int k, uint64_t seed, double* probs,
+                           int64_t* counts, int64_t* off, int64_t* btot, uint64_t* child, int64_t* cw, int64_t cap,
+                           hipStream_t st);
+hipError_t launch_bas_root(uint64_t* pre, int64_t* w, int W, int64_t n_samples, int64_t* u0, int64_t* overflow,
                            hipStream_t st);
 
 // Statistics and gradient (FP64).

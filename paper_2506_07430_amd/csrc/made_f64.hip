@@ -418,11 +418,12 @@ __global__ void __launch_bounds__(256)
 // FP64 network, 16 prefixes per wave (the layout of the FP64 sample pass).
 template <int HMAX, int NW>
 __global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, HiddenCaps caps,
-                                                   const uint64_t* __restrict__ pre, int64_t U, int k,
-                                                   double* __restrict__ probs) {
+                                                   const uint64_t* __restrict__ pre, const int64_t* __restrict__ Ud,
+                                                   int64_t cap, int k, double* __restrict__ probs) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t b0 = wave * 16;
+  const int64_t U = min(*Ud, cap);
   if (b0 >= U) return;
   const int n = S.n, na = S.na, nb = S.nb;
   const int64_t rb = b0 + r16;
@@ -544,9 +545,9 @@ hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream
 }
 
 template <int HMAX>
-static hipError_t bas_probs_h(const SysDev& S, const MadeDev& M, const uint64_t* pre, int64_t U, int k, double* probs,
-                              hipStream_t st) {
-  const int64_t waves = (U + 15) / 16;
+static hipError_t bas_probs_h(const SysDev& S, const MadeDev& M, const uint64_t* pre, const int64_t* Ud, int64_t cap,
+                              int k, double* probs, hipStream_t st) {
+  const int64_t waves = (cap + 15) / 16;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
   // orbital k's logits see the last hidden layer's units of degree <= k, and a hidden unit
   // of degree d only units of degree <= d below it: in every hidden layer the units of
@@ -558,18 +559,20 @@ static hipError_t bas_probs_h(const SysDev& S, const MadeDev& M, const uint64_t*
     for (int r = 0; r < q && r < k; ++r) cnt += (w > r) ? (w - r - 1) / q + 1 : 0;   // degree r + 1 <= k
     caps.nob[l] = (cnt + 15) / 16;
   }
-  if (S.W == 1) hipLaunchKernelGGL((k_bas_probs<HMAX, 1>), dim3(blocks), dim3(256), 0, st, S, M, caps, pre, U, k, probs);
-  else hipLaunchKernelGGL((k_bas_probs<HMAX, 2>), dim3(blocks), dim3(256), 0, st, S, M, caps, pre, U, k, probs);
+  if (S.W == 1)
+    hipLaunchKernelGGL((k_bas_probs<HMAX, 1>), dim3(blocks), dim3(256), 0, st, S, M, caps, pre, Ud, cap, k, probs);
+  else
+    hipLaunchKernelGGL((k_bas_probs<HMAX, 2>), dim3(blocks), dim3(256), 0, st, S, M, caps, pre, Ud, cap, k, probs);
   return hipGetLastError();
 }
 
-hipError_t launch_bas_probs(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, int64_t U, int k,
-                            double* probs, hipStream_t st) {
+hipError_t launch_bas_probs(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* Ud,
+                            int64_t cap, int k, double* probs, hipStream_t st) {
   switch (hmax) {
-    case 32: return bas_probs_h<32>(S, M, pre, U, k, probs, st);
-    case 64: return bas_probs_h<64>(S, M, pre, U, k, probs, st);
-    case 128: return bas_probs_h<128>(S, M, pre, U, k, probs, st);
-    case 256: return bas_probs_h<256>(S, M, pre, U, k, probs, st);
+    case 32: return bas_probs_h<32>(S, M, pre, Ud, cap, k, probs, st);
+    case 64: return bas_probs_h<64>(S, M, pre, Ud, cap, k, probs, st);
+    case 128: return bas_probs_h<128>(S, M, pre, Ud, cap, k, probs, st);
+    case 256: return bas_probs_h<256>(S, M, pre, Ud, cap, k, probs, st);
   }
   return hipErrorInvalidValue;
 }

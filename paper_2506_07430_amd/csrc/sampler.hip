@@ -2,11 +2,14 @@
 //
 // The N_s samples are a tree of unique prefixes with multiplicities. For orbital k:
 // the FP64 ansatz gives every prefix its number-conserving conditional over the four
-// occupations of orbital k; every prefix splits its weight w by w independent
-// categorical draws (uniforms from Philox4x32-10 at counter (draw, prefix, k, 0) and key
-// (seed)); children with no draws are pruned and the rest listed in (prefix, state)
-// order by an exclusive scan. The draw counts are integer sums, so the tree does not
-// depend on scheduling.
+// occupations of orbital k; every prefix splits its weight w among the occupations by one
+// multinomial draw (a chain of binomials, one thread per prefix), so a step costs the same
+// for any N_s; children with no draws are pruned and the rest listed in (prefix, state)
+// order by an exclusive scan. The uniforms come from Philox4x32-10 at counter
+// (attempt, prefix, k, state) and key (seed), so the tree does not depend on scheduling.
+// The prefix counts live in device memory: no step waits for the host.
+#include <cmath>
+
 #include "elocal_internal.hpp"
 #include "kernels.hpp"
 
@@ -30,147 +33,159 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   }
 }
 
-__device__ __forceinline__ double bas_uniform(uint32_t j, uint32_t i, uint32_t k, uint64_t seed) {
-  uint32_t c[4] = {j, i, k, 0u};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-  const uint64_t bits = (((uint64_t)c[0] << 32) | c[1]) >> 11;
-  return (double)bits * 0x1.0p-53;
+// The two uniforms in [0, 1) of attempt t of the binomial of state st of prefix i at
+// orbital k: the 53 high bits of words (0, 1) and of words (2, 3).
+struct UniformStream {
+  uint32_t i, k, st;
+  uint64_t seed;
+  __device__ __forceinline__ void pair(uint32_t t, double& u1, double& u2) const {
+    uint32_t c[4] = {t, i, k, st};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    u1 = (double)((((uint64_t)c[0] << 32) | c[1]) >> 11) * 0x1.0p-53;
+    u2 = (double)((((uint64_t)c[2] << 32) | c[3]) >> 11) * 0x1.0p-53;
+  }
+};
+
+// The binomial arithmetic below is written as plain FP64 operations in a fixed order, not
+// contracted into fused multiply-adds, so its rounding is that of the same expressions
+// evaluated one operation at a time.
+#pragma clang fp contract(off)
+
+// Stirling-series correction f_c(k) = ln k! - (k + 1/2) ln(k + 1) + (k + 1) - ln(2 pi)/2
+// of the BTRD acceptance test (Hormann 1993): from its definition below 10, else from the
+// series 1/12 - 1/360 (k+1)^-2 + 1/1260 (k+1)^-4, over (k + 1).
+__device__ double stirling_fc(double k) {
+  if (k < 10.0) return lgamma(k + 1.0) - (k + 0.5) * log(k + 1.0) + (k + 1.0) - 0.5 * log(2.0 * M_PI);
+  const double kk = 1.0 / ((k + 1.0) * (k + 1.0));
+  return (1.0 / 12.0 - (1.0 / 360.0 - 1.0 / 1260.0 * kk) * kk) / (k + 1.0);
 }
+
+// Binomial(n, p) with p <= 1/2: inversion from K = 0 when n p < 10 (an attempt that runs
+// past the last representable pmf term is retried with the next uniforms), otherwise the
+// transformed rejection with decomposition BTRD (W. Hormann, "The generation of binomial
+// random variates", J. Stat. Comput. Simul. 46, 1993). n < 2^53.
+__device__ int64_t binomial_small_p(int64_t n, double p, const UniformStream& rs) {
+  const double nf = (double)n;
+  uint32_t t = 0;
+  if (nf * p < 10.0) {
+    const double s = p / (1.0 - p), a = (nf + 1.0) * s, f0 = exp(nf * log1p(-p));
+    for (;;) {
+      double u, unused;
+      rs.pair(t++, u, unused);
+      double f = f0;
+      int64_t kk = 0;
+      bool ran_out = false;
+      while (u > f) {
+        u -= f;
+        ++kk;
+        f *= a / (double)kk - s;
+        if (f <= 0.0 || kk > n) { ran_out = true; break; }
+      }
+      if (!ran_out || (u <= f && kk <= n)) return kk;
+    }
+  }
+  const double m = floor((nf + 1.0) * p);
+  const double r = p / (1.0 - p), nr = (nf + 1.0) * r, npq = nf * p * (1.0 - p), spq = sqrt(npq);
+  const double b = 1.15 + 2.53 * spq, a = -0.0873 + 0.0248 * b + 0.01 * p, c = nf * p + 0.5;
+  const double alpha = (2.83 + 5.1 / b) * spq, vr = 0.92 - 4.2 / b, urvr = 0.86 * vr;
+  for (;;) {
+    double v, u2, u;
+    rs.pair(t++, v, u2);
+    if (v <= urvr) {
+      u = v / vr - 0.43;
+      const double kf = floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
+      if (kf >= 0.0 && kf <= nf) return (int64_t)kf;
+      continue;
+    }
+    if (v >= vr) {
+      u = u2 - 0.5;
+    } else {
+      u = v / vr - 0.93;
+      u = (u > 0.0 ? 0.5 : -0.5) - u;
+      v = u2 * vr;
+    }
+    const double us = 0.5 - fabs(u);
+    const double kf = floor((2.0 * a / us + b) * u + c);
+    if (kf < 0.0 || kf > nf) continue;
+    v = v * alpha / (a / (us * us) + b);
+    const double km = fabs(kf - m);
+    if (km <= 15.0) {
+      double f = 1.0;
+      if (m < kf) {
+        for (double i = m + 1.0; i <= kf; i += 1.0) f *= nr / i - r;
+      } else if (m > kf) {
+        for (double i = kf + 1.0; i <= m; i += 1.0) v *= nr / i - r;
+      }
+      if (v <= f) return (int64_t)kf;
+      continue;
+    }
+    v = log(v);
+    const double rho = (km / npq) * (((km / 3.0 + 0.625) * km + 1.0 / 6.0) / npq + 0.5);
+    const double tt = -km * km / (2.0 * npq);
+    if (v < tt - rho) return (int64_t)kf;
+    if (v > tt + rho) continue;
+    const double nm = nf - m + 1.0;
+    const double h = (m + 0.5) * log((m + 1.0) / (r * nm)) + stirling_fc(m) + stirling_fc(nf - m);
+    const double nk = nf - kf + 1.0;
+    if (v <= h + (nf + 1.0) * log(nm / nk) + (kf + 0.5) * log(nk * r / (kf + 1.0)) - stirling_fc(kf) -
+                  stirling_fc(nf - kf))
+      return (int64_t)kf;
+  }
+}
+
+__device__ int64_t binomial(int64_t n, double p, const UniformStream& rs) {
+  if (n <= 0 || p <= 0.0) return 0;
+  if (p >= 1.0) return n;
+  if (p > 0.5) return n - binomial_small_p(n, 1.0 - p, rs);
+  return binomial_small_p(n, p, rs);
+}
+
+#pragma clang fp contract(on)
 
 // ----------------------------------------------------------------------------- kernels
-// Draw counts of prefix i (gridDim.y blocks per prefix): counts[i][s].
-__global__ void __launch_bounds__(256) k_bas_counts(const double* __restrict__ probs, const int64_t* __restrict__ w,
-                                                    int k, uint64_t seed, int64_t* __restrict__ counts) {
-  __shared__ unsigned long long cnt[4];
-  const int64_t i = blockIdx.x;
-  if (threadIdx.x < 4) cnt[threadIdx.x] = 0ull;
-  __syncthreads();
-  const double p0 = probs[4 * i], p1 = probs[4 * i + 1], p2 = probs[4 * i + 2], p3 = probs[4 * i + 3];
-  // running sums over the reachable states, in state order
-  const double pr[4] = {p0, p1, p2, p3};
-  double run[4];
-  int last = -1;
-  double acc = 0.0;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (pr[s] > 0.0) {
-      acc = acc + pr[s];
-      last = s;
-    }
-    run[s] = acc;
-  }
-  unsigned long long c[4] = {0ull, 0ull, 0ull, 0ull};
-  const int64_t wi = w[i];
-  // draws j of prefix i: this block takes j = y * 256 + thread (mod 256 gridDim.y)
-  const int64_t stride = (int64_t)blockDim.x * gridDim.y;
-  for (int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; j < wi; j += stride) {
-    const double u = bas_uniform((uint32_t)j, (uint32_t)i, (uint32_t)k, seed);
-    int cat = last;
-#pragma unroll
-    for (int s = 3; s >= 0; --s)
-      if (pr[s] > 0.0 && u < run[s]) cat = s;
-    if (cat >= 0) c[cat]++;
-  }
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-    if (c[s]) atomicAdd(&cnt[s], c[s]);
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    if (gridDim.y == 1) counts[4 * i + threadIdx.x] = (int64_t)cnt[threadIdx.x];
-    else if (cnt[threadIdx.x]) atomicAdd((unsigned long long*)&counts[4 * i + threadIdx.x], cnt[threadIdx.x]);
-  }
-}
-
-__global__ void k_bas_zero(int64_t* __restrict__ p, int64_t n) {
+// Multinomial split of every prefix's weight over the four occupations of orbital k, one
+// thread per prefix: the feasible states (probability > 0) in ascending order take
+// binomials of what is left with probability p_s / (sum of the remaining p, in ascending
+// order); the last feasible state takes the rest. counts[i][s].
+#pragma clang fp contract(off)
+__global__ void __launch_bounds__(256) k_bas_split(const double* __restrict__ probs, const int64_t* __restrict__ w,
+                                                   const int64_t* __restrict__ ucur, int64_t cap, int k,
+                                                   uint64_t seed, int64_t* __restrict__ counts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
-// Exclusive scan of the prefix weights within blocks of 1024 (woff), and the block totals.
-__global__ void __launch_bounds__(1024) k_bas_wscan_blocks(const int64_t* __restrict__ w, int64_t U,
-                                                           int64_t* __restrict__ woff, int64_t* __restrict__ btot) {
-  __shared__ int64_t s[1024];
-  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  const int64_t v = i < U ? w[i] : 0;
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int64_t t = threadIdx.x >= (unsigned)d ? s[threadIdx.x - d] : 0;
-    __syncthreads();
-    s[threadIdx.x] += t;
-    __syncthreads();
-  }
-  if (i < U) woff[i] = s[threadIdx.x] - v;
-  if (threadIdx.x == 1023) btot[blockIdx.x] = s[1023];
-}
-
-// Draw counts over the flat draw index: draw j of the step belongs to the prefix i whose
-// weight range [off_i, off_i + w_i) holds j (off: block offsets boff, then woff within the
-// block), and is draw j - off_i of that prefix, so it uses the same uniform as in
-// k_bas_counts. Many prefixes with few draws each then cost one thread per draw instead of
-// one block per prefix. A wave whose draws all fall in one prefix adds its four counts once;
-// otherwise every draw adds 1 (integer atomics: the totals do not depend on their order).
-__global__ void __launch_bounds__(256) k_bas_counts_flat(const double* __restrict__ probs,
-                                                         const int64_t* __restrict__ woff,
-                                                         const int64_t* __restrict__ boff, int64_t nblk, int64_t U,
-                                                         const int64_t* __restrict__ total, int k, uint64_t seed,
-                                                         int64_t* __restrict__ counts) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = *total;
-  const bool live = j < N;
-  int64_t i = 0, jl = 0;
-  int cat = -1;
-  if (live) {
-    // block: the last b with boff[b] <= j (boff ascending, boff[0] = 0)
-    int64_t lo = 0, hi = nblk - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (boff[mid] <= j) lo = mid; else hi = mid - 1;
-    }
-    const int64_t b = lo, r = j - boff[b];
-    int64_t l0 = b * 1024, l1 = (b * 1024 + 1023 < U ? b * 1024 + 1023 : U - 1);
-    while (l0 < l1) {
-      const int64_t mid = (l0 + l1 + 1) >> 1;
-      if (woff[mid] <= r) l0 = mid; else l1 = mid - 1;
-    }
-    i = l0;
-    jl = r - woff[i];
-    const double p0 = probs[4 * i], p1 = probs[4 * i + 1], p2 = probs[4 * i + 2], p3 = probs[4 * i + 3];
-    const double pr[4] = {p0, p1, p2, p3};
-    double run[4];
-    double acc = 0.0;
+  if (i >= min(*ucur, cap)) return;
+  double p[4];
+  int last = -1;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (pr[q] > 0.0) {
-        acc = acc + pr[q];
-        cat = q;
-      }
-      run[q] = acc;
-    }
-    const double u = bas_uniform((uint32_t)jl, (uint32_t)i, (uint32_t)k, seed);
-#pragma unroll
-    for (int q = 3; q >= 0; --q)
-      if (pr[q] > 0.0 && u < run[q]) cat = q;
+  for (int q = 0; q < 4; ++q) {
+    p[q] = probs[4 * i + q];
+    if (p[q] > 0.0) last = q;
   }
-  const int64_t i0 = __shfl(i, 0);
-  const uint64_t act = __ballot(live && cat >= 0);
-  if (__ballot(live && cat >= 0 && i == i0) == act) {   // one prefix for the whole wave
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t m = __ballot(live && cat == q);
-      if (lane == 0 && m) atomicAdd((unsigned long long*)&counts[4 * i0 + q], (unsigned long long)__popcll(m));
-    }
-  } else if (live && cat >= 0) {
-    atomicAdd((unsigned long long*)&counts[4 * i + cat], 1ull);
+  int64_t left = w[i];
+  int64_t c[4] = {0, 0, 0, 0};
+  UniformStream rs{(uint32_t)i, (uint32_t)k, 0u, seed};
+  for (int q = 0; q < last; ++q) {
+    if (!(p[q] > 0.0)) continue;
+    double rem = 0.0;
+    for (int q2 = q; q2 < 4; ++q2)
+      if (p[q2] > 0.0) rem = rem + p[q2];
+    rs.st = (uint32_t)q;
+    const int64_t cq = binomial(left, fmin(1.0, p[q] / rem), rs);
+    c[q] = cq;
+    left -= cq;
   }
+  if (last >= 0) c[last] = left;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) counts[4 * i + q] = c[q];
 }
+#pragma clang fp contract(on)
 
 // Number of surviving children per prefix, and their exclusive scan (blocks of 1024,
 // then the block totals, then the block offsets added).
-__global__ void __launch_bounds__(1024) k_bas_scan_blocks(const int64_t* __restrict__ counts, int64_t U,
+__global__ void __launch_bounds__(1024) k_bas_scan_blocks(const int64_t* __restrict__ counts,
+                                                          const int64_t* __restrict__ ucur, int64_t cap,
                                                           int64_t* __restrict__ off, int64_t* __restrict__ btot) {
   __shared__ int64_t s[1024];
+  const int64_t U = min(*ucur, cap);
   const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   int64_t v = 0;
   if (i < U)
@@ -188,7 +203,8 @@ __global__ void __launch_bounds__(1024) k_bas_scan_blocks(const int64_t* __restr
 }
 
 __global__ void __launch_bounds__(1024) k_bas_scan_totals(int64_t* __restrict__ btot, int64_t nblk,
-                                                          int64_t* __restrict__ total) {
+                                                          int64_t* __restrict__ total, int64_t cap,
+                                                          int64_t* __restrict__ overflow) {
   __shared__ int64_t s[1024];
   int64_t carry = 0;
   for (int64_t base = 0; base < nblk; base += 1024) {
@@ -206,15 +222,19 @@ __global__ void __launch_bounds__(1024) k_bas_scan_totals(int64_t* __restrict__ 
     carry += s[1023];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) {
+    *total = carry;
+    if (overflow && carry > cap) *overflow = 1;
+  }
 }
 
 template <int NW>
-__global__ void k_bas_emit(const uint64_t* __restrict__ pre, const int64_t* __restrict__ counts, int64_t U, int k,
-                           const int64_t* __restrict__ off, const int64_t* __restrict__ btot,
-                           uint64_t* __restrict__ child, int64_t* __restrict__ cw, int64_t cap) {
+__global__ void k_bas_emit(const uint64_t* __restrict__ pre, const int64_t* __restrict__ counts,
+                           const int64_t* __restrict__ ucur, int k, const int64_t* __restrict__ off,
+                           const int64_t* __restrict__ btot, uint64_t* __restrict__ child, int64_t* __restrict__ cw,
+                           int64_t cap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= U) return;
+  if (i >= min(*ucur, cap)) return;
   int64_t o = off[i] + btot[i / 1024];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -235,37 +255,38 @@ __global__ void k_bas_emit(const uint64_t* __restrict__ pre, const int64_t* __re
   }
 }
 
-// ----------------------------------------------------------------------------- launchers
-hipError_t launch_bas_step(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* w,
-                           int64_t U, int k, uint64_t seed, double* probs, int64_t* counts, int64_t* off,
-                           int64_t* btot, int64_t* total, uint64_t* child, int64_t* cw, int64_t cap, int64_t ndraws,
-                           hipStream_t st) {
-  if (U <= 0 || ndraws <= 0) return hipErrorInvalidValue;
-  hipError_t e = launch_bas_probs(S, M, hmax, pre, U, k, probs, st);
-  if (e != hipSuccess) return e;
-  // few prefixes (the first orbitals) carry all the draws: their draws are spread over up
-  // to 64 blocks each, whose integer counts are added atomically (order-independent)
-  const unsigned ysplit = U >= 2048 ? 1u : (unsigned)(2048 / U < 64 ? 2048 / U : 64);
-  const int64_t nblk = (U + 1023) / 1024;
-  hipLaunchKernelGGL(k_bas_zero, dim3((unsigned)((4 * U + 255) / 256)), dim3(256), 0, st, counts, 4 * U);
-  if (U < 2048) {
-    hipLaunchKernelGGL(k_bas_counts, dim3((unsigned)U, ysplit), dim3(256), 0, st, probs, w, k, seed, counts);
-  } else {
-    // many prefixes: one thread per draw over the flat draw index (off, btot and total are
-    // free until the children's scan below)
-    hipLaunchKernelGGL(k_bas_wscan_blocks, dim3((unsigned)nblk), dim3(1024), 0, st, w, U, off, btot);
-    hipLaunchKernelGGL(k_bas_scan_totals, dim3(1), dim3(1024), 0, st, btot, nblk, total);
-    hipLaunchKernelGGL(k_bas_counts_flat, dim3((unsigned)((ndraws + 255) / 256)), dim3(256), 0, st, probs, off, btot,
-                       nblk, U, total, k, seed, counts);
+__global__ void k_bas_root(uint64_t* pre, int64_t* w, int W, int64_t n_samples, int64_t* u0, int64_t* overflow) {
+  if (threadIdx.x < (unsigned)W) pre[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) {
+    w[0] = n_samples;
+    *u0 = 1;
+    *overflow = 0;
   }
-  hipLaunchKernelGGL(k_bas_scan_blocks, dim3((unsigned)nblk), dim3(1024), 0, st, counts, U, off, btot);
-  hipLaunchKernelGGL(k_bas_scan_totals, dim3(1), dim3(1024), 0, st, btot, nblk, total);
+}
+
+// ----------------------------------------------------------------------------- launchers
+hipError_t launch_bas_root(uint64_t* pre, int64_t* w, int W, int64_t n_samples, int64_t* u0, int64_t* overflow,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_bas_root, dim3(1), dim3(64), 0, st, pre, w, W, n_samples, u0, overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_bas_step(const SysDev& S, const MadeDev& M, int hmax, const uint64_t* pre, const int64_t* w,
+                           const int64_t* ucur, int64_t* unext, int64_t* overflow, int k, uint64_t seed, double* probs,
+                           int64_t* counts, int64_t* off, int64_t* btot, uint64_t* child, int64_t* cw, int64_t cap,
+                           hipStream_t st) {
+  if (cap <= 0) return hipErrorInvalidValue;
+  hipError_t e = launch_bas_probs(S, M, hmax, pre, ucur, cap, k, probs, st);
+  if (e != hipSuccess) return e;
+  const int64_t nblk = (cap + 1023) / 1024;
+  const unsigned tb = (unsigned)((cap + 255) / 256);
+  hipLaunchKernelGGL(k_bas_split, dim3(tb), dim3(256), 0, st, probs, w, ucur, cap, k, seed, counts);
+  hipLaunchKernelGGL(k_bas_scan_blocks, dim3((unsigned)nblk), dim3(1024), 0, st, counts, ucur, cap, off, btot);
+  hipLaunchKernelGGL(k_bas_scan_totals, dim3(1), dim3(1024), 0, st, btot, nblk, unext, cap, overflow);
   if (S.W == 1)
-    hipLaunchKernelGGL(k_bas_emit<1>, dim3((unsigned)((U + 255) / 256)), dim3(256), 0, st, pre, counts, U, k, off, btot,
-                       child, cw, cap);
+    hipLaunchKernelGGL(k_bas_emit<1>, dim3(tb), dim3(256), 0, st, pre, counts, ucur, k, off, btot, child, cw, cap);
   else
-    hipLaunchKernelGGL(k_bas_emit<2>, dim3((unsigned)((U + 255) / 256)), dim3(256), 0, st, pre, counts, U, k, off, btot,
-                       child, cw, cap);
+    hipLaunchKernelGGL(k_bas_emit<2>, dim3(tb), dim3(256), 0, st, pre, counts, ucur, k, off, btot, child, cw, cap);
   return hipGetLastError();
 }
 

@@ -1,8 +1,12 @@
 """Batch autoregressive sampling on the GPU (elocal_sample) against the BAS oracle.
 
-Both sides draw from the same Philox4x32-10 stream with the same categorical rule on
-FP64 conditionals, so the distinct samples, their order and their counts must be equal
-(bit-exact). At scale the counts follow |psi|^2 (chi-square over the full sector).
+Both sides split every prefix's weight by the same chain of binomials (inversion or BTRD)
+from the same Philox4x32-10 stream on FP64 conditionals, so the distinct samples, their
+order and their counts must be equal (bit-exact) at moderate N_s. At N_s = 10^12 an ulp of
+difference between the two sides' FP64 conditionals can move a binomial variate by one
+(its mean n p is then known to 1e-4 only), so there the leaves must be the same and the
+counts agree to 1e-6 relative; the counts follow |psi|^2 (chi-square over the full sector)
+and the call takes about as long as at N_s = 10^5 (its cost follows the distinct prefixes).
 """
 import time
 
@@ -38,6 +42,37 @@ def test_sampler_equals_oracle(cfg, Ns, seed):
     print(f"workload {cfg}: {Ns} draws -> {x.shape[0]} distinct (oracle {occ.shape[0]})")
     assert np.array_equal(words_from_dev(x), osc.pack(occ))
     assert np.array_equal(c.cpu().numpy(), cnt)
+
+
+def test_sampler_at_1e12_draws():
+    from scipy.stats import chi2
+    p = synth.make_problem(0)
+    s = p.system
+    ham = make_ham(p)
+    th_dev, th = theta_for(p.theta, elocal.FP64)
+    ans = elocal.Ansatz(s.widths, th_dev, elocal.FP64)
+    ham.sample(ans, 1000, 1)
+    times = {}
+    for Ns in (10 ** 5, 10 ** 12):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, c = ham.sample(ans, Ns, 17)
+        times[Ns] = time.perf_counter() - t0
+    print(f"N_s = 1e5: {times[10 ** 5] * 1e3:.2f} ms, N_s = 1e12: {times[10 ** 12] * 1e3:.2f} ms, "
+          f"{x.shape[0]} distinct", flush=True)
+    assert int(c.sum().item()) == 10 ** 12
+    occ, cnt = osamp.bas(th, s.n, s.n_alpha, s.n_beta, s.widths, 10 ** 12, 17)
+    assert np.array_equal(words_from_dev(x), osc.pack(occ))
+    cg = c.cpu().numpy()
+    assert np.max(np.abs(cg - cnt) / cnt) < 1e-6
+    sector = synth.full_sector(s)
+    A = omade.forward(th, osc.unpack(sector, s.n), s.n, s.n_alpha, s.n_beta, s.widths)["A"]
+    exp = 1e12 * np.exp(2 * A)
+    obs = np.zeros(sector.shape[0])
+    obs[np.searchsorted(sector[:, 0], words_from_dev(x)[:, 0])] = cg
+    stat = np.sum((obs - exp) ** 2 / exp)
+    assert chi2.sf(stat, sector.shape[0] - 1) > 1e-6, stat
+    assert times[10 ** 12] < 5 * times[10 ** 5] + 0.05
 
 
 def test_sampler_frequencies_at_scale():
