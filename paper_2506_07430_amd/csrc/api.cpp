@@ -447,9 +447,9 @@ size_t carve_grad(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, void* ws,
   for (int l = 0; l <= L + 1; ++l) P.h[l] = c.take<double>(Bs * P.dims[l]);
   P.d0 = c.take<double>(Bs * maxdim);
   P.d1 = c.take<double>(Bs * maxdim);
-  P.ones = c.take<double>(Bs);
   P.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, B / 256));
   P.part = c.take<double>((size_t)P.splits * maxw);
+  P.part_per_split = (int64_t)maxw;
   P.T = G.T;
   P.precision = G.precision;
   if (out) *out = P;

@@ -188,8 +188,8 @@ struct GradPlan {
   double* h[kMaxLayers + 1];   // activations: h[0] = bits [B][2n], h[l] [B][dims[l]], h[L+1] logits
   double* d0;                  // [B][maxdim] backward buffers
   double* d1;
-  double* part;                // split-K partials
-  double* ones;                // [B]
+  double* part;                // split-K partials: splits x part_per_split doubles
+  int64_t part_per_split;
   double* dW[kMaxLayers];      // [out][in]
   double* db[kMaxLayers];      // [out]
   int splits;
