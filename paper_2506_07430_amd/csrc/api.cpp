@@ -271,7 +271,7 @@ struct EvalPlan {
   bool ldsw;
   StagePlan stage;  // BF16: which layers are staged (biases follow the weights, then the
                     // wave contexts and the input table)
-  bool inplace;     // BF16: hidden layers updated in place (see inplace_ok)
+  bool inplace;     // hidden layers updated in place (see inplace_ok, inplace_ok_f64)
   size_t lds;
   int cols;         // BF16: 16-row tiles per network pass (kernel variant)
   int waves;        // waves per block
@@ -334,6 +334,17 @@ static bool inplace_ok(const MadeDev& M) {
   return true;
 }
 
+// FP64 in-place hidden layers are exact when o-block ob of every hidden layer reads no
+// input block beyond ob + 1 (its k-steps, rounded up to whole chunks of 4, <= 4 (ob + 2)).
+static bool inplace_ok_f64(const MadeDev& M) {
+  for (int l = 1; l < M.L; ++l)
+    for (int ob = 0; ob < M.nob[l]; ++ob) {
+      const int kw = std::min(M.nk[l], (M.kend[l][ob] + 3) / 4 * 4);
+      if (kw > 4 * (ob + 2)) return false;
+    }
+  return true;
+}
+
 EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t list_len = -1) {
   EvalPlan p{};
   // BF16: groups of 64 entries (one per lane), 8 per item; FP64: tiles of 16, 16 per item
@@ -360,6 +371,7 @@ EvalPlan plan_eval(const elocal_ctx* h, const AnsatzGeom& G, int64_t B, int64_t 
     p.lds = 0;
     p.cols = 1;
     p.waves = 4;
+    p.inplace = G.hmax >= 128 && inplace_ok_f64(G.md);
   }
   const int64_t want = (p.n_items + p.waves - 1) / p.waves;
   p.grid = (unsigned)std::max<int64_t>(1, std::min(want, grid_cap(h, p.waves)));
@@ -684,7 +696,7 @@ elocal_status elocal_eval(elocal_t h, elocal_stream s, const elocal_ansatz* a, c
     HIP_TRY(launch_eval_bf16(E, G.hmax, G.nterms, p.cols, p.ldsw, p.inplace, p.lds, p.grid, p.waves, st),
             "eval launch");
   } else {
-    HIP_TRY(launch_eval_f64(E, G.hmax, p.grid, st), "eval launch");
+    HIP_TRY(launch_eval_f64(E, G.hmax, p.inplace, p.grid, st), "eval launch");
   }
   if (timed) {
     HIP_TRY(hipEventRecord(h->ev_stop[slot], st), "timing event");

@@ -124,7 +124,9 @@ hipError_t launch_store_bytes(const void* src, size_t bytes, void* dst, hipStrea
 hipError_t launch_pack_f64(const MadeDev& M, const ThetaLayout& T, const double* theta,
                            void* frag, double* bias, hipStream_t st);
 hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st);
-hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream_t st);
+// inplace: the two-waves-per-SIMD variant with in-place hidden layers (widths 128 and 256;
+// the caller checks that the network allows it)
+hipError_t launch_eval_f64(const EvalArgs& A, int hmax, bool inplace, unsigned grid, hipStream_t st);
 
 // Sum of the per-item partials plus the diagonal: eloc[b] = ediag[b] + sum_s partial[b][s].
 hipError_t launch_reduce(const double* ediag, const double* partial, int64_t B, uint32_t ips,

@@ -62,12 +62,6 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, const f64x4& c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ f64x4 load_bias4_64(const double* bias, uint32_t off) {
-  f64x4 r;
-  r[0] = bias[off]; r[1] = bias[off + 1]; r[2] = bias[off + 2]; r[3] = bias[off + 3];
-  return r;
-}
-
 __device__ __forceinline__ f64x4 relu4(const f64x4& a) {
   f64x4 r;
 #pragma unroll
@@ -75,19 +69,57 @@ __device__ __forceinline__ f64x4 relu4(const f64x4& a) {
   return r;
 }
 
-// k-steps [0, ke) of one o-block: f(ks, w) with w = wp[64 ks], the weight loads running
+// Weight loads of the FP64 network. From global memory through a buffer resource: the
+// lane's byte offset stays in one VGPR and the fragment's offset is a scalar, so the
+// unrolled k-loops keep no 64-bit address per k-step live (with two waves per SIMD those
+// addresses alone would not fit); a load past the packed buffer returns zero.
+struct WGlobal64 {
+  __amdgpu_buffer_rsrc_t r;
+  uint32_t voff;    // lane * 8
+  uint32_t frag0;   // the o-block's first fragment
+  __device__ __forceinline__ double operator()(int ks) const {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, (frag0 + (uint32_t)ks) * 512u, 0);
+    double d;
+    __builtin_memcpy(&d, &v, 8);
+    return d;
+  }
+};
+// From LDS (or any pointer): fragment ks of the o-block at p (p includes the lane).
+struct WPtr64 {
+  const double* p;
+  __device__ __forceinline__ double operator()(int ks) const { return p[ks * 64]; }
+};
+// Biases of rows 4g..4g+3 of the 16-row block starting at padded bias `blk`: two 16-byte
+// loads with the lane's offset in a VGPR and the block's as a scalar.
+__device__ __forceinline__ f64x4 bias4_rsrc(const __amdgpu_buffer_rsrc_t& r, uint32_t voff_g, uint32_t blk) {
+  const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff_g, blk * 8u, 0);
+  const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff_g + 16u, blk * 8u, 0);
+  double d[4];
+  __builtin_memcpy(d, &lo, 16);
+  __builtin_memcpy(d + 2, &hi, 16);
+  return f64x4{d[0], d[1], d[2], d[3]};
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bias_rsrc64(const MadeDev& M) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(M.bias), (short)0, (int)(M.nbias * 8u), 0x00020000);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t weight_rsrc64(const MadeDev& M) {
+  // word 3 = 0x00020000: raw (untyped) buffer access on the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(M.wfrag), (short)0, (int)(M.nfrag * 512u), 0x00020000);
+}
+
+// k-steps [0, ke) of one o-block: f(ks, w) with w = ld(ks), the weight loads running
 // two chunks of CH k-steps ahead of the products that use them (one wave per SIMD has
 // nothing else to hide the load latency with). CH = 8 measured best at width <= 128;
 // width 256 keeps CH = 4 (fewer registers).
-template <int KSMAX, int CH, class F>
-__device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke, F&& f) {
+template <int KSMAX, int CH, class Ld, class F>
+__device__ __forceinline__ void kloop_f64(const Ld& ld, int ke, F&& f) {
   constexpr int LA = 2, NC = (KSMAX + CH - 1) / CH;
   double w[NC][CH];
 #pragma unroll
   for (int c = 0; c < LA && c < NC; ++c)
 #pragma unroll
     for (int j = 0; j < CH; ++j)
-      if (c * CH + j < ke) w[c][j] = wp[(c * CH + j) * 64];
+      if (c * CH + j < ke) w[c][j] = ld(c * CH + j);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     // keeps the scheduler from hoisting later chunks' loads (their registers) above this point
@@ -96,7 +128,7 @@ __device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke,
       if (c + LA < NC) {
 #pragma unroll
         for (int j = 0; j < CH; ++j)
-          if ((c + LA) * CH + j < ke) w[c + LA][j] = wp[((c + LA) * CH + j) * 64];
+          if ((c + LA) * CH + j < ke) w[c + LA][j] = ld((c + LA) * CH + j);
       }
 #pragma unroll
       for (int j = 0; j < CH; ++j)
@@ -107,15 +139,15 @@ __device__ __forceinline__ void kloop_f64(const double* __restrict__ wp, int ke,
 
 // As kloop_f64 for a block whose k-range is whole chunks (ke a multiple of CH, at most the
 // block's stored k-steps): one branch per chunk instead of one per k-step.
-template <int KSMAX, int CH, class F>
-__device__ __forceinline__ void kloop_f64_whole(const double* __restrict__ wp, int ke, F&& f) {
+template <int KSMAX, int CH, class Ld, class F>
+__device__ __forceinline__ void kloop_f64_whole(const Ld& ld, int ke, F&& f) {
   constexpr int LA = 2, NC = (KSMAX + CH - 1) / CH;
   double w[NC][CH];
 #pragma unroll
   for (int c = 0; c < LA && c < NC; ++c)
     if (c * CH < ke) {
 #pragma unroll
-      for (int j = 0; j < CH; ++j) w[c][j] = wp[(c * CH + j) * 64];
+      for (int j = 0; j < CH; ++j) w[c][j] = ld(c * CH + j);
     }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -123,7 +155,7 @@ __device__ __forceinline__ void kloop_f64_whole(const double* __restrict__ wp, i
     if (c * CH < ke) {
       if (c + LA < NC && (c + LA) * CH < ke) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j) w[c + LA][j] = wp[((c + LA) * CH + j) * 64];
+        for (int j = 0; j < CH; ++j) w[c + LA][j] = ld((c + LA) * CH + j);
       }
 #pragma unroll
       for (int j = 0; j < CH; ++j) f(c * CH + j, w[c][j]);
@@ -137,19 +169,30 @@ struct HiddenCaps {
 };
 
 // Network on one 16-row block (row r of lane r); epi(ob, acc) per output block ob in
-// [ob_lo, ob_hi) (all of them by default). W: packed weights (layer l at fragment woff[l]);
-// WL: the output layer's fragment 0, which may be a copy in LDS. With CAP only the first
+// [ob_lo, ob_hi) (all of them by default). Weights come from the packed buffer M.wfrag
+// (layer l at fragment woff[l]); with OUT_LDS the output layer's come from WL, a copy of its
+// fragments in LDS. With CAP only the first
 // caps.nob[l] blocks of hidden layer l are computed and the others are zero (a block the
 // caller needs must not depend on the skipped ones).
-template <int HMAX, int NW, bool CAP = false, class Epi>
-__device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ W,
-                                        const double* __restrict__ WL, const double* __restrict__ bias,
+//
+// With INPLACE the hidden layers keep one activation array: output blocks are computed from
+// the highest down, and block ob + 1's result waits in a register set until block ob has
+// read its inputs; it then overwrites input block ob + 1, which no lower block reads. Exact
+// when every block ob of a hidden layer reads input blocks <= ob + 1 (inplace_ok_f64 on the
+// host); half the activation registers, so two waves fit per SIMD at widths 128 and 256.
+template <int HMAX, int NW, bool CAP = false, bool INPLACE = false, bool OUT_LDS = false, class Epi>
+__device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restrict__ WL,
                                         const uint64_t (&xr)[NW], int lane, Epi&& epi, int ob_lo = 0,
                                         int ob_hi = kMaxOutBlocks, const HiddenCaps& caps = HiddenCaps{}) {
+  static_assert(!(CAP && INPLACE), "capped layers are computed out of place");
   constexpr int OB = HMAX / 16;
   constexpr int KS = HMAX / 4;
-  constexpr int KCH = HMAX >= 256 ? 4 : 8;   // k-steps per weight-load chunk
+  // k-steps per weight-load chunk (the in-place variant's row of chunks is what its
+  // exactness condition assumes)
+  constexpr int KCH = (HMAX >= 256 || INPLACE) ? 4 : 8;
   const int g = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rs = weight_rsrc64(M), rb = bias_rsrc64(M);
+  const uint32_t voff = (uint32_t)lane * 8u, voff_g = (uint32_t)g * 32u;
   f64x4 cur[OB];
   {
     const int nk = M.nk[0], nob = CAP ? min(M.nob[0], caps.nob[0]) : M.nob[0];
@@ -158,25 +201,42 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
       if (CAP && ob >= nob) cur[ob] = f64x4{0.0, 0.0, 0.0, 0.0};
       if (ob < nob) {
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[0][ob]);
-        f64x4 acc = load_bias4_64(bias, M.boff[0] + 16 * ob + 4 * g);
-        const double* wp = W + (size_t)(M.woff[0] + ob * nk) * 64 + lane;
+        f64x4 acc = bias4_rsrc(rb, voff_g, M.boff[0] + 16 * ob);
+        const WGlobal64 wl{rs, voff, M.woff[0] + (uint32_t)(ob * nk)};
         if constexpr (NW == 1 && HMAX <= 128) {
           // one-word determinants (2n <= 64 bits, at most 16 k-steps): loads run ahead
-          kloop_f64<16, 4>(wp, ke, [&](int ks, double w) {
+          kloop_f64<16, 4>(wl, ke, [&](int ks, double w) {
             acc = mfma_f64(w, (double)getbit<NW>(xr, 4 * ks + g), acc);
           });
         } else {
           // longer inputs or wider networks: the registers for prefetching are not there
           for (int ks = 0; ks < ke; ++ks) {
             const double bv = (double)getbit<NW>(xr, 4 * ks + g);
-            acc = mfma_f64(wp[ks * 64], bv, acc);
+            acc = mfma_f64(wl(ks), bv, acc);
           }
         }
         cur[ob] = relu4(acc);
       }
     }
   }
-  for (int l = 1; l < M.L; ++l) {
+  for (int l = 1; l < M.L && INPLACE; ++l) {
+    const int nk = M.nk[l], nob = M.nob[l];
+    f64x4 pend = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ob = OB - 1; ob >= 0; --ob) {
+      if (ob < nob) {
+        const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
+        f64x4 acc = bias4_rsrc(rb, voff_g, M.boff[l] + 16 * ob);
+        const WGlobal64 wl{rs, voff, M.woff[l] + (uint32_t)(ob * nk)};
+        const int kw = min(nk, (ke + KCH - 1) / KCH * KCH);
+        kloop_f64_whole<KS, KCH>(wl, kw, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+        if (ob + 1 < nob) cur[ob + 1] = pend;
+        pend = relu4(acc);
+      }
+    }
+    cur[0] = pend;
+  }
+  for (int l = 1; l < M.L && !INPLACE; ++l) {
     const int nk = M.nk[l], nob = CAP ? min(M.nob[l], caps.nob[l]) : M.nob[l];
     f64x4 nxt[OB];
 #pragma unroll
@@ -184,12 +244,12 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
       if (CAP && ob >= nob) nxt[ob] = f64x4{0.0, 0.0, 0.0, 0.0};
       if (ob < nob) {
         const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
-        f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
-        const double* wp = W + (size_t)(M.woff[l] + ob * nk) * 64 + lane;
+        f64x4 acc = bias4_rsrc(rb, voff_g, M.boff[l] + 16 * ob);
+        const WGlobal64 wl{rs, voff, M.woff[l] + (uint32_t)(ob * nk)};
         // whole chunks: the extra k-steps up to a chunk boundary hold masked (zero) weights,
         // and nk (width / 4, widths are multiples of 32) is a multiple of the chunk
         const int kw = min(nk, (ke + KCH - 1) / KCH * KCH);
-        kloop_f64_whole<KS, KCH>(wp, kw, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+        kloop_f64_whole<KS, KCH>(wl, kw, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
         nxt[ob] = relu4(acc);
       }
     }
@@ -201,10 +261,11 @@ __device__ __forceinline__ void mlp_f64(const MadeDev& M, const double* __restri
 #pragma unroll 1
     for (int ob = ob_lo; ob < nob; ++ob) {
       const int ke = __builtin_amdgcn_readfirstlane(M.kend[l][ob]);
-      f64x4 acc = load_bias4_64(bias, M.boff[l] + 16 * ob + 4 * g);
-      const double* wp = WL + (size_t)(ob * nk) * 64 + lane;
+      f64x4 acc = bias4_rsrc(rb, voff_g, M.boff[l] + 16 * ob);
       const int kw = min(nk, (ke + KCH - 1) / KCH * KCH);   // whole chunks, as above
-      kloop_f64_whole<KS, KCH>(wp, kw, [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); });
+      auto step = [&](int ks, double w) { acc = mfma_f64(w, cur[ks >> 2][ks & 3], acc); };
+      if constexpr (OUT_LDS) kloop_f64_whole<KS, KCH>(WPtr64{WL + (size_t)(ob * nk) * 64 + lane}, kw, step);
+      else kloop_f64_whole<KS, KCH>(WGlobal64{rs, voff, M.woff[l] + (uint32_t)(ob * nk)}, kw, step);
       epi(ob, acc);
     }
   }
@@ -254,8 +315,7 @@ __global__ void __launch_bounds__(256) k_rows_f64(RowsArgs P) {
   for (int w = 0; w < NW; ++w) xr[w] = P.x[bb * NW + w];
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
   double A = 0.0, zp = 0.0;
-  mlp_f64<HMAX, NW>(M, (const double*)M.wfrag, (const double*)M.wfrag + (size_t)M.woff[M.L] * 64,
-                    (const double*)M.bias, xr, lane,
+  mlp_f64<HMAX, NW>(M, nullptr, xr, lane,
                     [&](int ob, const f64x4& a) {
                       const int p = 4 * ob + g;
                       if (p < n) {
@@ -292,13 +352,11 @@ struct SampleState64 {
 
 // One work item = one sample and P.tpi tiles of 16 list entries; the 64 lanes of a tile
 // share its 16 rows (lane group g holds output units 4g..4g+3 of each 16-unit block).
-template <int HMAX, int NW>
+template <int HMAX, int NW, bool INPLACE = false, bool OUT_LDS = false>
 __device__ __forceinline__ void eval_item_f64(const EvalArgs& P, const double* __restrict__ WL, WaveCtx64& wc,
                                               int64_t item, SampleState64<NW>& st, int lane) {
   const MadeDev& M = P.made;
   const SysDev& S = P.sys;
-  const double* W = (const double*)M.wfrag;
-  const double* bias = (const double*)M.bias;
   const int g = lane >> 4, r16 = lane & 15;
   const int n = S.n, na = S.na, nb = S.nb;
   const int ob_phi = (4 * n) >> 4, g_phi = ((4 * n) & 15) >> 2;
@@ -337,7 +395,7 @@ __device__ __forceinline__ void eval_item_f64(const EvalArgs& P, const double* _
     }
     const int p0 = first_diff_orbital<NW>(xs, xp, n);
     double dA = 0.0, zp = 0.0;
-    mlp_f64<HMAX, NW>(M, W, WL, bias, xp, lane, [&](int ob, const f64x4& a) {
+    mlp_f64<HMAX, NW, false, INPLACE, OUT_LDS>(M, WL, xp, lane, [&](int ob, const f64x4& a) {
       const int p = 4 * ob + g;
       if (p < n && p >= p0) dA += cond_logp64<NW>(xp, p, n, na, nb, a) - wc.lpx[p];
       if (ob == ob_phi && g == g_phi) zp = a[0];
@@ -366,9 +424,11 @@ __device__ __forceinline__ void eval_item_f64(const EvalArgs& P, const double* _
 }
 
 // With LDSO the output layer's packed weights are first copied to LDS (dynamic shared
-// memory of nob[L] * nk[L] fragments).
-template <int HMAX, int NW, bool LDSO>
-__global__ void __launch_bounds__(256) k_eval_f64(EvalArgs P) {
+// memory of nob[L] * nk[L] fragments). The in-place variant is built for two waves per
+// SIMD (256 registers per lane).
+template <int HMAX, int NW, bool LDSO, bool INPLACE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(INPLACE ? 2 : 1)))
+k_eval_f64(EvalArgs P) {
   __shared__ WaveCtx64 ctxs[4];
   extern __shared__ __attribute__((aligned(16))) double wout[];
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -383,7 +443,7 @@ __global__ void __launch_bounds__(256) k_eval_f64(EvalArgs P) {
   SampleState64<NW> st;
   st.b = -1;
   for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < P.n_items; item += (int64_t)gridDim.x * 4)
-    eval_item_f64<HMAX, NW>(P, WL, ctxs[wid], item, st, lane);
+    eval_item_f64<HMAX, NW, INPLACE, LDSO>(P, WL, ctxs[wid], item, st, lane);
 }
 
 // Several systems in one persistent launch (item index space as in the BF16 kernel).
@@ -407,10 +467,8 @@ __global__ void __launch_bounds__(256)
     }
     const EvalArgs& P = args[s];
     const int64_t local = item - first[s];
-    if (P.sys.W == 1) eval_item_f64<HMAX, 1>(P, (const double*)P.made.wfrag + (size_t)P.made.woff[P.made.L] * 64, ctxs[wid],
-                                                 local, st1, lane);
-    else eval_item_f64<HMAX, 2>(P, (const double*)P.made.wfrag + (size_t)P.made.woff[P.made.L] * 64, ctxs[wid],
-                                            local, st2, lane);
+    if (P.sys.W == 1) eval_item_f64<HMAX, 1>(P, nullptr, ctxs[wid], local, st1, lane);
+    else eval_item_f64<HMAX, 2>(P, nullptr, ctxs[wid], local, st2, lane);
   }
 }
 
@@ -431,8 +489,7 @@ __global__ void __launch_bounds__(256) k_bas_probs(SysDev S, MadeDev M, HiddenCa
   uint64_t xr[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) xr[w] = pre[bb * NW + w];
-  mlp_f64<HMAX, NW, true>(M, (const double*)M.wfrag, (const double*)M.wfrag + (size_t)M.woff[M.L] * 64,
-                          (const double*)M.bias, xr, lane, [&](int ob, const f64x4& z) {
+  mlp_f64<HMAX, NW, true>(M, nullptr, xr, lane, [&](int ob, const f64x4& z) {
     if (4 * ob + g != k) return;
     const int cu = count_spin_below<NW>(xr, k, 0), cd = count_spin_below<NW>(xr, k, 1);
     const int left = n - k - 1;
@@ -485,34 +542,39 @@ hipError_t launch_rows_f64(const RowsArgs& A, int hmax, hipStream_t st) {
 }
 
 // Launches k_eval_f64 with the output layer in LDS when it fits beside the kernel's
-// static LDS (one 4-wave block per CU), else reading it from global memory.
-template <int HMAX, int NW>
+// static LDS (one 4-wave block per CU; two for the in-place variant, which has half the
+// LDS each), else reading it from global memory.
+template <int HMAX, int NW, bool INPLACE>
 static hipError_t eval_f64_nw(const EvalArgs& A, unsigned grid, hipStream_t st) {
-  constexpr size_t kLds = 160 * 1024;
+  constexpr size_t kLds = (INPLACE ? 80 : 160) * 1024;
   static size_t static_lds = ~(size_t)0;   // a property of the code object: the same on every device
   if (static_lds == ~(size_t)0) {
     hipFuncAttributes fa;
-    const hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_eval_f64<HMAX, NW, true>);
+    const hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_eval_f64<HMAX, NW, true, INPLACE>);
     if (e != hipSuccess) return e;
     static_lds = fa.sharedSizeBytes;
   }
   const size_t out = (size_t)A.made.nob[A.made.L] * A.made.nk[A.made.L] * 64 * sizeof(double);
   if (static_lds + out <= kLds) {
     if (out > 65536) {
-      const hipError_t e = hipFuncSetAttribute((const void*)k_eval_f64<HMAX, NW, true>,
+      const hipError_t e = hipFuncSetAttribute((const void*)k_eval_f64<HMAX, NW, true, INPLACE>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)out);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_eval_f64<HMAX, NW, true>), dim3(grid), dim3(256), out, st, A);
+    hipLaunchKernelGGL((k_eval_f64<HMAX, NW, true, INPLACE>), dim3(grid), dim3(256), out, st, A);
   } else {
-    hipLaunchKernelGGL((k_eval_f64<HMAX, NW, false>), dim3(grid), dim3(256), 0, st, A);
+    hipLaunchKernelGGL((k_eval_f64<HMAX, NW, false, INPLACE>), dim3(grid), dim3(256), 0, st, A);
   }
   return hipGetLastError();
 }
 
 template <int HMAX>
-static hipError_t eval_f64_h(const EvalArgs& A, unsigned grid, hipStream_t st) {
-  return A.sys.W == 1 ? eval_f64_nw<HMAX, 1>(A, grid, st) : eval_f64_nw<HMAX, 2>(A, grid, st);
+static hipError_t eval_f64_h(const EvalArgs& A, bool inplace, unsigned grid, hipStream_t st) {
+  if constexpr (HMAX >= 128) {
+    if (inplace)
+      return A.sys.W == 1 ? eval_f64_nw<HMAX, 1, true>(A, grid, st) : eval_f64_nw<HMAX, 2, true>(A, grid, st);
+  }
+  return A.sys.W == 1 ? eval_f64_nw<HMAX, 1, false>(A, grid, st) : eval_f64_nw<HMAX, 2, false>(A, grid, st);
 }
 
 template <int HMAX>
@@ -533,13 +595,13 @@ hipError_t launch_eval_multi_f64(const EvalArgs* args, const int64_t* first, int
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_eval_f64(const EvalArgs& A, int hmax, unsigned grid, hipStream_t st) {
+hipError_t launch_eval_f64(const EvalArgs& A, int hmax, bool inplace, unsigned grid, hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
   switch (hmax) {
-    case 32: return eval_f64_h<32>(A, grid, st);
-    case 64: return eval_f64_h<64>(A, grid, st);
-    case 128: return eval_f64_h<128>(A, grid, st);
-    case 256: return eval_f64_h<256>(A, grid, st);
+    case 32: return eval_f64_h<32>(A, false, grid, st);
+    case 64: return eval_f64_h<64>(A, false, grid, st);
+    case 128: return eval_f64_h<128>(A, inplace, grid, st);
+    case 256: return eval_f64_h<256>(A, inplace, grid, st);
   }
   return hipErrorInvalidValue;
 }
