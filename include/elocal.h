@@ -346,10 +346,11 @@ elocal_status elocal_check_samples(elocal_t h, elocal_stream s, const uint64_t* 
                                    void* ws, size_t ws_bytes, int64_t* n_bad);
 
 /*
- * Timing of the dominant kernel (the fused local-energy kernel of elocal_eval).
- * When enabled, each elocal_eval on the handle (and each elocal_eval_multi whose first
- * handle it is) records a pair of HIP events around that kernel on the caller's stream
- * (a ring of 1024 pairs, reused in order).
+ * Timing of the dominant kernel (the fused local-energy kernel of elocal_eval; the
+ * generator kernel of elocal_connect, without its per-sample preparation).
+ * When enabled, each elocal_eval or elocal_connect on the handle (and each
+ * elocal_eval_multi whose first handle it is) records a pair of HIP events around that
+ * kernel on the caller's stream (a ring of 1024 pairs, reused in order).
  * elocal_kernel_timing waits for the recorded events, returns the summed milliseconds
  * and the number of launches recorded since the last reset (reset != 0 clears them).
  * These two calls mutate the handle: do not overlap them with other calls on it.

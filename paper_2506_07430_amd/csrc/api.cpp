@@ -652,7 +652,14 @@ elocal_status elocal_connect(elocal_t h, elocal_stream s, const uint64_t* x, int
   const ConnectWs w = carve_connect(h, B, ws);
   hipStream_t st = (hipStream_t)s;
   HIP_TRY(launch_prep(h->sys, x, B, w.ediag, w.F, st), "prep launch");
+  const int slot = (int)(h->ring_pos % elocal_ctx::kRing);
+  if (h->timing) HIP_TRY(hipEventRecord(h->ev_start[slot], st), "timing event");
   HIP_TRY(launch_connect(h->sys, x, B, w.ediag, w.F, xp, hval, sign, exc, st), "connect launch");
+  if (h->timing) {
+    HIP_TRY(hipEventRecord(h->ev_stop[slot], st), "timing event");
+    h->ring_pos++;
+    h->recorded++;
+  }
   return ELOCAL_OK;
 }
 

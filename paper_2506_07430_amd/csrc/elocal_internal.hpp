@@ -254,14 +254,15 @@ __device__ __forceinline__ double excitation_value(const SysDev& S, const Excita
   switch (e.kind) {
     case KIND_DIAG: return ed;
     case KIND_SINGLE: return Fs[e.sidx];
+    // 32-bit table indices: n <= 64, so n^4 < 2^25
     case KIND_DOUBLE_SAME: {
-      const size_t ab = (size_t)e.a * n + e.b;
-      const double d = S.S[((size_t)e.i * n + e.j) * n * n + ab];
-      const double x = S.S[((size_t)e.j * n + e.i) * n * n + ab];
+      const uint32_t nn = (uint32_t)(n * n), ab = (uint32_t)(e.a * n + e.b);
+      const double d = S.S[(uint32_t)(e.i * n + e.j) * nn + ab];
+      const double x = S.S[(uint32_t)(e.j * n + e.i) * nn + ab];
       return d - x;
     }
     default:
-      return S.S[(((size_t)e.i * n + e.j) * n + e.a) * n + e.b];
+      return S.S[(uint32_t)(((e.i * n + e.j) * n + e.a) * n + e.b)];
   }
 }
 

@@ -72,8 +72,9 @@ __device__ __forceinline__ ListEntry<NW> list_entry(const SysDev& S, const Sampl
   const double v = excitation_value(S, e, Fs, ed);
   r.h = sg < 0 ? -v : v;
   r.sg = (int8_t)sg;
-  r.code = (uint32_t)(e.I < 0 ? 0xFF : e.I) | ((uint32_t)(e.J < 0 ? 0xFF : e.J) << 8) |
-           ((uint32_t)(e.A < 0 ? 0xFF : e.A) << 16) | ((uint32_t)(e.Bq < 0 ? 0xFF : e.Bq) << 24);
+  // unused slots hold -1, whose low byte is the 0xFF marker
+  r.code = ((uint32_t)e.I & 0xFFu) | (((uint32_t)e.J & 0xFFu) << 8) | (((uint32_t)e.A & 0xFFu) << 16) |
+           ((uint32_t)e.Bq << 24);
   return r;
 }
 
