@@ -324,12 +324,16 @@ static StagePlan plan_stage(const AnsatzGeom& G, int kernel_hmax, int waves, siz
 }
 
 // In-place hidden layers are exact when o-block pair j of every hidden layer reads no
-// k-block beyond j + 1 (its second block's kend <= j + 2).
+// k-block beyond j + 1 (both blocks' kend <= j + 2). The in-place kernels also take both
+// blocks' first j + 1 k-blocks without a test, so they need kend >= j + 1 as well (true of
+// every degree-sorted network whose hidden layers have one width).
 static bool inplace_ok(const MadeDev& M) {
   for (int l = 1; l < M.L; ++l)
     for (int j = 0; 2 * j < M.nob[l]; ++j) {
-      const int ke = std::max(M.kend[l][2 * j], 2 * j + 1 < M.nob[l] ? M.kend[l][2 * j + 1] : 0);
-      if (ke > j + 2) return false;
+      const bool two = 2 * j + 1 < M.nob[l];
+      const int ke = std::max(M.kend[l][2 * j], two ? M.kend[l][2 * j + 1] : 0);
+      const int kl = two ? std::min(M.kend[l][2 * j], M.kend[l][2 * j + 1]) : M.kend[l][2 * j];
+      if (ke > j + 2 || kl < j + 1) return false;
     }
   return true;
 }

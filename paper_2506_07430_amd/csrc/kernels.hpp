@@ -101,8 +101,10 @@ constexpr int kLdsPartialWidth = 256;
 // LDS a fused BF16 block of `waves` waves needs beyond the staged weights and biases.
 constexpr size_t block_lds_bf16(int waves) { return (size_t)waves * kWaveCtxBytesBF16 + kXLutBytes; }
 // Hidden layers updated in place (INPLACE) exist for the widest two-term kernels, whose
-// waves run two per SIMD in 256 registers; the host uses them when every hidden layer's
-// o-block pair j reads no k-block beyond j + 1.
+// waves run two per SIMD in 256 registers; the host uses them when o-block pair j of every
+// hidden layer reads at least j + 1 and at most j + 2 k-blocks (then one activation array
+// suffices and the pair's k-loop has one runtime test). At width 128 the in-place variant
+// measured 2% slower, so it is not built there.
 constexpr bool inplace_kernel_bf16(int hmax, int nterms) { return hmax >= kLdsPartialWidth && nterms == 2; }
 // Several systems in one launch: args[s] describes system s (device copy). BF16: system
 // s owns chunks [first[s], first[s+1]) of `waves` work items each (LDS layout as

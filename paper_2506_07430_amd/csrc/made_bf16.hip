@@ -233,13 +233,12 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restr
   const h16x8* wp = W + (size_t)sgpr(M.foff[l][ob]) * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
-    if (kb == 0 || kb < ke) {
-      const h16x8 w = wp[kb * 64];
+    if (kb > 0 && kb >= ke) break;   // the k-range is a prefix: one exit, no test per later k-block
+    const h16x8 w = wp[kb * 64];
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int i = 0; i < NT; ++i) a[c] = mfma_f16(w, act[i][c][kb], a[c]);
-    }
+      for (int i = 0; i < NT; ++i) a[c] = mfma_f16(w, act[i][c][kb], a[c]);
   }
 }
 
@@ -247,11 +246,15 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restr
 // mask keeps, into a0 (block 2 kbo) and a1 (block 2 kbo + 1), which arrive holding the
 // biases. With PREFETCH (NT = 2) the fragment loads are issued in chunks of four k-blocks,
 // one chunk ahead of the products.
+// kmin <= kend <= kcap for both blocks of the pair, bounds known where the call is unrolled
+// (kbo + 1 and kbo + 2 for the in-place layers, whose host check guarantees them; 1 and KB
+// otherwise), so that the k-blocks below kmin run without a test and those from kcap on are
+// dropped at compile time.
 template <int KB, int NT, int NC, bool PREFETCH>
 __device__ __forceinline__ void hidden_pair(const MadeDev& M, const h16x8* __restrict__ W, int l, int kbo,
                                             const h16x8 (&act)[NT][NC][KB], int lane, f32x4 (&a0)[NC],
-                                            f32x4 (&a1)[NC]) {
-  const int ke0 = sgpr(M.kend[l][2 * kbo]), ke1 = sgpr(M.kend[l][2 * kbo + 1]);
+                                            f32x4 (&a1)[NC], int kmin = 1, int kcap = KB) {
+  const int ke0 = min(sgpr(M.kend[l][2 * kbo]), kcap), ke1 = min(sgpr(M.kend[l][2 * kbo + 1]), kcap);
   const h16x8* w0p = W + (size_t)sgpr(M.foff[l][2 * kbo]) * 64 + lane;
   const h16x8* w1p = W + (size_t)sgpr(M.foff[l][2 * kbo + 1]) * 64 + lane;
   if constexpr (PREFETCH) {
@@ -260,30 +263,30 @@ __device__ __forceinline__ void hidden_pair(const MadeDev& M, const h16x8* __res
 #pragma unroll
     for (int j = 0; j < CH; ++j) {   // prologue: chunk 0
       const int kb = j;
-      if (kb == 0 || kb < ke1) w1b[0][j] = w1p[kb * 64];
-      if (kb == 0 || kb < ke0) w0b[0][j] = w0p[kb * 64];
+      if (kb < kmin || (kb < kcap && kb < ke1)) w1b[0][j] = w1p[kb * 64];
+      if (kb < kmin || (kb < kcap && kb < ke0)) w0b[0][j] = w0p[kb * 64];
     }
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       __builtin_amdgcn_sched_barrier(0);
-      if (c * CH < ke1) {
+      if (c * CH < kmin || (c * CH < kcap && c * CH < ke1)) {
         if (c + 1 < NCH) {
 #pragma unroll
           for (int j = 0; j < CH; ++j) {
             const int kb = (c + 1) * CH + j;
-            if (kb < ke1) w1b[c + 1][j] = w1p[kb * 64];
-            if (kb < ke0) w0b[c + 1][j] = w0p[kb * 64];
+            if (kb < kmin || (kb < kcap && kb < ke1)) w1b[c + 1][j] = w1p[kb * 64];
+            if (kb < kmin || (kb < kcap && kb < ke0)) w0b[c + 1][j] = w0p[kb * 64];
           }
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
           const int kb = c * CH + j;
-          if (kb < KB && (kb == 0 || kb < ke1)) {
+          if (kb < KB && (kb < kmin || (kb < kcap && kb < ke1))) {
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
               for (int i = 0; i < NT; ++i) a1[cc] = mfma_f16(w1b[c][j], act[i][cc][kb], a1[cc]);
-            if (kb == 0 || kb < ke0) {
+            if (kb < kmin || (kb < kcap && kb < ke0)) {
 #pragma unroll
               for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
@@ -296,13 +299,13 @@ __device__ __forceinline__ void hidden_pair(const MadeDev& M, const h16x8* __res
   } else {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      if (kb == 0 || kb < ke1) {
+      if (kb < kmin || (kb < kcap && kb < ke1)) {
         const h16x8 w1 = w1p[kb * 64];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
           for (int i = 0; i < NT; ++i) a1[c] = mfma_f16(w1, act[i][c][kb], a1[c]);
-        if (kb == 0 || kb < ke0) {
+        if (kb < kmin || (kb < kcap && kb < ke0)) {
           const h16x8 w0 = w0p[kb * 64];
 #pragma unroll
           for (int c = 0; c < NC; ++c)
@@ -338,7 +341,7 @@ __device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __re
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        hidden_pair<KB, NT, NC, PREFETCH>(M, W, l, kbo, act, lane, a0, a1);
+        hidden_pair<KB, NT, NC, PREFETCH>(M, W, l, kbo, act, lane, a0, a1, kbo + 1, kbo + 2);
         if (kbo + 1 < KB && 2 * (kbo + 1) < nob) {
 #pragma unroll
           for (int i = 0; i < NT; ++i)
@@ -451,13 +454,12 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-              if (kb == 0 || kb < ke1) {
+              if (kb > 0 && kb >= ke1) break;   // ke0 <= ke1: degrees grow along the layer
 #pragma unroll
-                for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(wb[kbo & 1][1][kb], xin[c][kb], a1[c]);
-                if (kb == 0 || kb < ke0) {
+              for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(wb[kbo & 1][1][kb], xin[c][kb], a1[c]);
+              if (kb == 0 || kb < ke0) {
 #pragma unroll
-                  for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(wb[kbo & 1][0][kb], xin[c][kb], a0[c]);
-                }
+                for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(wb[kbo & 1][0][kb], xin[c][kb], a0[c]);
               }
             }
           } else {
@@ -465,15 +467,14 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
             const h16x8* w1p = W + (size_t)sgpr(M.foff[0][2 * kbo + 1]) * 64 + lane;
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-              if (kb == 0 || kb < ke1) {
-                const h16x8 w1 = w1p[kb * 64];
+              if (kb > 0 && kb >= ke1) break;   // ke0 <= ke1
+              const h16x8 w1 = w1p[kb * 64];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(w1, xin[c][kb], a1[c]);
-                if (kb == 0 || kb < ke0) {
-                  const h16x8 w0 = w0p[kb * 64];
+              for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(w1, xin[c][kb], a1[c]);
+              if (kb == 0 || kb < ke0) {
+                const h16x8 w0 = w0p[kb * 64];
 #pragma unroll
-                  for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
-                }
+                for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
               }
             }
           }
@@ -519,12 +520,11 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
         for (int c = 0; c < NC; ++c) a[c] = b4;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-          if (kb == 0 || kb < ke) {
+          if (kb > 0 && kb >= ke) break;
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
+          for (int c = 0; c < NC; ++c)
 #pragma unroll
-              for (int i = 0; i < NT; ++i) a[c] = mfma_f16(wsrc[kb], act[i][c][kb], a[c]);
-          }
+            for (int i = 0; i < NT; ++i) a[c] = mfma_f16(wsrc[kb], act[i][c][kb], a[c]);
         }
         epi(ob, a);
       };
@@ -1110,7 +1110,7 @@ hipError_t launch_eval_bf16(const EvalArgs& A, int hmax, int nterms, int cols, b
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), lds, st, A);
         return hipGetLastError();
       };
-      // in-place hidden layers only where a wave's registers are short (the widest networks)
+      // in-place hidden layers where the variant is built and the network allows them
       if constexpr (inplace_kernel_bf16(HMAX, NT) && NC == 1) {
         if (inplace) {
           if (A.sys.W == 1)
