@@ -299,19 +299,19 @@ __device__ __forceinline__ void hidden_pair(const MadeDev& M, const h16x8* __res
   } else {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      if (kb < kmin || (kb < kcap && kb < ke1)) {
-        const h16x8 w1 = w1p[kb * 64];
+      // ke0 <= ke1 (degrees grow along the layer): one exit once block 1's range ends
+      if (kb >= kmin && (kb >= kcap || kb >= ke1)) break;
+      const h16x8 w1 = w1p[kb * 64];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < NT; ++i) a1[c] = mfma_f16(w1, act[i][c][kb], a1[c]);
+      if (kb < kmin || (kb < kcap && kb < ke0)) {
+        const h16x8 w0 = w0p[kb * 64];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int i = 0; i < NT; ++i) a1[c] = mfma_f16(w1, act[i][c][kb], a1[c]);
-        if (kb < kmin || (kb < kcap && kb < ke0)) {
-          const h16x8 w0 = w0p[kb * 64];
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int i = 0; i < NT; ++i) a0[c] = mfma_f16(w0, act[i][c][kb], a0[c]);
-        }
+          for (int i = 0; i < NT; ++i) a0[c] = mfma_f16(w0, act[i][c][kb], a0[c]);
       }
     }
   }
@@ -433,7 +433,8 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
         const h16x8* w1p = W + (size_t)sgpr(M.foff[0][2 * kbo + 1]) * 64 + lane;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          if (kb == 0 || kb < ke1) dst[1][kb] = w1p[kb * 64];
+          if (kb > 0 && kb >= ke1) break;   // ke0 <= ke1
+          dst[1][kb] = w1p[kb * 64];
           if (kb == 0 || kb < ke0) dst[0][kb] = w0p[kb * 64];
         }
       };
@@ -509,8 +510,10 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
         const int ke = sgpr(M.kend[l][ob]);
         const h16x8* wp = W + (size_t)sgpr(M.foff[l][ob]) * 64 + lane;
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-          if (kb == 0 || kb < ke) dst[kb] = wp[kb * 64];
+        for (int kb = 0; kb < KB; ++kb) {
+          if (kb > 0 && kb >= ke) break;
+          dst[kb] = wp[kb * 64];
+        }
       };
       auto run_block = [&](int ob, const h16x8 (&wsrc)[KB]) {
         const int ke = sgpr(M.kend[l][ob]);
