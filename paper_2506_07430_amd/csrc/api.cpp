@@ -222,6 +222,13 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
     }
   }
   if (bf) {
+    // layer 0 runs its o-blocks in pairs over one k-range, the pair's larger one (the first
+    // block's extra fragments hold masked zeros); an unpaired last block is paired with a
+    // phantom block of the same range
+    for (int j = 0; 2 * j < M.nob[0]; ++j) {
+      const int ke = 2 * j + 1 < M.nob[0] ? std::max(M.kend[0][2 * j], M.kend[0][2 * j + 1]) : M.kend[0][2 * j];
+      M.kend[0][2 * j] = M.kend[0][2 * j + 1] = ke;
+    }
     // compact BF16 packing: only the k-blocks each o-block uses
     uint32_t f = 0;
     for (int l = 0; l <= L; ++l) {

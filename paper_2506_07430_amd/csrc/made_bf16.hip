@@ -427,22 +427,23 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
       // multiplied (two buffers, all of a pair's at most 4 k-blocks at once)
       constexpr bool G0 = !decltype(in_lds)::value && PF;
       h16x8 wb[G0 ? 2 : 1][2][4];
+      // the two blocks of a pair share one k-range (the host pads the pair's first block)
       auto load_pair = [&](int kbo, h16x8 (&dst)[2][4]) {
-        const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
+        const int ke = sgpr(M.kend[0][2 * kbo + 1]);
         const h16x8* w0p = W + (size_t)sgpr(M.foff[0][2 * kbo]) * 64 + lane;
         const h16x8* w1p = W + (size_t)sgpr(M.foff[0][2 * kbo + 1]) * 64 + lane;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          if (kb > 0 && kb >= ke1) break;   // ke0 <= ke1
+          if (kb > 0 && kb >= ke) break;
           dst[1][kb] = w1p[kb * 64];
-          if (kb == 0 || kb < ke0) dst[0][kb] = w0p[kb * 64];
+          dst[0][kb] = w0p[kb * 64];
         }
       };
       if constexpr (G0) load_pair(0, wb[0]);
 #pragma unroll
       for (int kbo = 0; kbo < KB; ++kbo) {
         if (2 * kbo < nob) {
-          const int ke0 = sgpr(M.kend[0][2 * kbo]), ke1 = sgpr(M.kend[0][2 * kbo + 1]);
+          const int ke = sgpr(M.kend[0][2 * kbo + 1]);   // both blocks of the pair
           f32x4 a0[NC], a1[NC];
           {
             const f32x4 b0 = load_bias4(bias, M.boff[0] + 32 * kbo + 4 * g);
@@ -455,28 +456,24 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-              if (kb > 0 && kb >= ke1) break;   // ke0 <= ke1: degrees grow along the layer
+              if (kb > 0 && kb >= ke) break;
 #pragma unroll
               for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(wb[kbo & 1][1][kb], xin[c][kb], a1[c]);
-              if (kb == 0 || kb < ke0) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(wb[kbo & 1][0][kb], xin[c][kb], a0[c]);
-              }
+              for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(wb[kbo & 1][0][kb], xin[c][kb], a0[c]);
             }
           } else {
             const h16x8* w0p = W + (size_t)sgpr(M.foff[0][2 * kbo]) * 64 + lane;
             const h16x8* w1p = W + (size_t)sgpr(M.foff[0][2 * kbo + 1]) * 64 + lane;
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-              if (kb > 0 && kb >= ke1) break;   // ke0 <= ke1
+              if (kb > 0 && kb >= ke) break;
               const h16x8 w1 = w1p[kb * 64];
 #pragma unroll
               for (int c = 0; c < NC; ++c) a1[c] = mfma_f16(w1, xin[c][kb], a1[c]);
-              if (kb == 0 || kb < ke0) {
-                const h16x8 w0 = w0p[kb * 64];
+              const h16x8 w0 = w0p[kb * 64];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
-              }
+              for (int c = 0; c < NC; ++c) a0[c] = mfma_f16(w0, xin[c][kb], a0[c]);
             }
           }
 #pragma unroll
