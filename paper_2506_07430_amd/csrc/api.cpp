@@ -242,6 +242,13 @@ elocal_status make_geom(const elocal_ctx* h, const elocal_ansatz* a, AnsatzGeom&
     }
     for (int l = L + 1; l < kMaxLayers; ++l)
       for (int ob = 0; ob <= kMaxOutBlocks; ++ob) M.foff[l][ob] = (int32_t)f;
+    // the k-ranges as 4-bit fields (a BF16 o-block has at most 8 k-blocks)
+    static_assert(kMaxOutBlocks <= 24, "three words of eight 4-bit k-ranges");
+    for (int l = 0; l < kMaxLayers; ++l) {
+      M.kpack[l][0] = M.kpack[l][1] = M.kpack[l][2] = 0;
+      for (int ob = 0; l <= L && ob < kMaxOutBlocks; ++ob)
+        M.kpack[l][ob / 8] |= (uint32_t)(M.kend[l][ob] & 15) << (4 * (ob % 8));
+    }
     M.nfrag = f;
     wo = f;
   }

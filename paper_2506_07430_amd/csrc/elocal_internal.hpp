@@ -81,6 +81,9 @@ struct MadeDev {
   // (32-bit so that a wave-uniform lookup is a scalar load)
   int32_t kend[kMaxLayers][kMaxOutBlocks];
   int32_t foff[kMaxLayers][kMaxOutBlocks + 1];
+  // BF16: kend[l][ob] again as 4-bit fields, eight per word (o-block ob in bits 4 (ob % 8)
+  // of word ob / 8), so that a loop over o-blocks reads its k-ranges from three registers
+  uint32_t kpack[kMaxLayers][3];
   const void* wfrag;           // packed weights (8 fp16 per lane or one double per lane)
   const void* bias;            // float (BF16 mode) or double (FP64 mode)
 };

@@ -186,6 +186,12 @@ __device__ __forceinline__ void split_relu(const f32x4& a, const f32x4& b, h16x8
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// k-range of o-block ob (wave-uniform) from the three packed words of its layer.
+__device__ __forceinline__ int kend_packed(uint32_t k0, uint32_t k1, uint32_t k2, int ob) {
+  const uint32_t w = ob < 8 ? k0 : ob < 16 ? k1 : k2;
+  return (int)((w >> (4 * (ob & 7))) & 15u);
+}
+
 __device__ __forceinline__ f32x4 mfma_f16(const h16x8& a, const h16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
@@ -503,19 +509,21 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
       // epilogue runs (two buffers, all of a block's k-blocks at once)
       const int l = M.L;
       h16x8 wv[2][KB];
-      auto load_block = [&](int ob, h16x8 (&dst)[KB]) {
-        const int ke = sgpr(M.kend[l][ob]);
-        const h16x8* wp = W + (size_t)sgpr(M.foff[l][ob]) * 64 + lane;
+      // k-ranges from three packed words read once, fragment offsets as a running sum
+      const uint32_t kp0 = (uint32_t)sgpr((int)M.kpack[l][0]), kp1 = (uint32_t)sgpr((int)M.kpack[l][1]),
+                     kp2 = (uint32_t)sgpr((int)M.kpack[l][2]);
+      const int bbase = sgpr((int)M.boff[l]);
+      auto load_block = [&](int ke, int fo, h16x8 (&dst)[KB]) {
+        const h16x8* wp = W + (size_t)fo * 64 + lane;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           if (kb > 0 && kb >= ke) break;
           dst[kb] = wp[kb * 64];
         }
       };
-      auto run_block = [&](int ob, const h16x8 (&wsrc)[KB]) {
-        const int ke = sgpr(M.kend[l][ob]);
+      auto run_block = [&](int ob, int ke, const h16x8 (&wsrc)[KB]) {
         f32x4 a[NC];
-        const f32x4 b4 = load_bias4(bias, M.boff[l] + 16 * ob + 4 * g);
+        const f32x4 b4 = load_bias4(bias, bbase + 16 * ob + 4 * g);
 #pragma unroll
         for (int c = 0; c < NC; ++c) a[c] = b4;
 #pragma unroll
@@ -529,17 +537,26 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
         epi(ob, a);
       };
       int ob = sgpr(ob_first);
-      if (ob < nob) load_block(ob, wv[0]);
+      int fo = ob < nob ? sgpr(M.foff[l][ob]) : 0;   // first fragment of block ob
+      int ke = kend_packed(kp0, kp1, kp2, ob);
+      if (ob < nob) load_block(ke, fo, wv[0]);
 #pragma unroll 1
       while (ob < nob) {
-        if (ob + 1 < nob) load_block(ob + 1, wv[1]);
+        int fo1 = fo + ke, ke1 = kend_packed(kp0, kp1, kp2, ob + 1);
+        if (ob + 1 < nob) load_block(ke1, fo1, wv[1]);
         __builtin_amdgcn_sched_barrier(0);
-        run_block(ob, wv[0]);
+        run_block(ob, ke, wv[0]);
         if (++ob >= nob) break;
-        if (ob + 1 < nob) load_block(ob + 1, wv[0]);
+        fo = fo1;
+        ke = ke1;
+        fo1 = fo + ke;
+        ke1 = kend_packed(kp0, kp1, kp2, ob + 1);
+        if (ob + 1 < nob) load_block(ke1, fo1, wv[0]);
         __builtin_amdgcn_sched_barrier(0);
-        run_block(ob, wv[1]);
+        run_block(ob, ke, wv[1]);
         ++ob;
+        fo = fo1;
+        ke = ke1;
       }
     } else {
 #pragma unroll 1
