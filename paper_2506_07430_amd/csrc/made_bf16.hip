@@ -228,15 +228,15 @@ constexpr bool lds_partial_bf16() { return HMAX >= kLdsPartialWidth; }
 
 // Output block ob of the last layer for the NC 16-row tiles (tile c: row r of lane r).
 // W: base such that fragment f of the packing is W[f * 64 + lane].
+// ke: the block's k-range, fo: its first fragment, bb: the layer's bias offset.
 template <int KB, int NT, int NC>
-__device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restrict__ W,
-                                          const float* __restrict__ bias, const h16x8 (&act)[NT][NC][KB],
-                                          int ob, int lane, f32x4 (&a)[NC]) {
-  const int l = M.L, ke = sgpr(M.kend[l][ob]);
-  const f32x4 b4 = load_bias4(bias, M.boff[l] + 16 * ob + 4 * (lane >> 4));
+__device__ __forceinline__ void out_block(const h16x8* __restrict__ W, const float* __restrict__ bias, int bb,
+                                          const h16x8 (&act)[NT][NC][KB], int ob, int ke, int fo, int lane,
+                                          f32x4 (&a)[NC]) {
+  const f32x4 b4 = load_bias4(bias, bb + 16 * ob + 4 * (lane >> 4));
 #pragma unroll
   for (int c = 0; c < NC; ++c) a[c] = b4;
-  const h16x8* wp = W + (size_t)sgpr(M.foff[l][ob]) * 64 + lane;
+  const h16x8* wp = W + (size_t)fo * 64 + lane;
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     if (kb > 0 && kb >= ke) break;   // the k-range is a prefix: one exit, no test per later k-block
@@ -256,13 +256,15 @@ __device__ __forceinline__ void out_block(const MadeDev& M, const h16x8* __restr
 // (kbo + 1 and kbo + 2 for the in-place layers, whose host check guarantees them; 1 and KB
 // otherwise), so that the k-blocks below kmin run without a test and those from kcap on are
 // dropped at compile time.
+// ke0, ke1: the blocks' k-ranges; f0, f1: their first fragments.
 template <int KB, int NT, int NC, bool PREFETCH>
-__device__ __forceinline__ void hidden_pair(const MadeDev& M, const h16x8* __restrict__ W, int l, int kbo,
+__device__ __forceinline__ void hidden_pair(const h16x8* __restrict__ W, int kbo, int ke0, int ke1, int f0, int f1,
                                             const h16x8 (&act)[NT][NC][KB], int lane, f32x4 (&a0)[NC],
                                             f32x4 (&a1)[NC], int kmin = 1, int kcap = KB) {
-  const int ke0 = min(sgpr(M.kend[l][2 * kbo]), kcap), ke1 = min(sgpr(M.kend[l][2 * kbo + 1]), kcap);
-  const h16x8* w0p = W + (size_t)sgpr(M.foff[l][2 * kbo]) * 64 + lane;
-  const h16x8* w1p = W + (size_t)sgpr(M.foff[l][2 * kbo + 1]) * 64 + lane;
+  ke0 = min(ke0, kcap);
+  ke1 = min(ke1, kcap);
+  const h16x8* w0p = W + (size_t)f0 * 64 + lane;
+  const h16x8* w1p = W + (size_t)f1 * 64 + lane;
   if constexpr (PREFETCH) {
     constexpr int CH = 4, NCH = (KB + CH - 1) / CH;
     h16x8 w0b[NCH][CH], w1b[NCH][CH];
@@ -334,20 +336,29 @@ __device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __re
                                              const float* __restrict__ bias, int l, int lane,
                                              h16x8 (&act)[NT][NC][HMAX / 32]) {
   constexpr int KB = HMAX / 32;
-  const int g = lane >> 4, nob = M.nob[l];
+  const int g = lane >> 4, nob = sgpr(M.nob[l]);
+  // the layer's k-ranges from three packed words, its bias offset, and fragment offsets as
+  // a running sum (a hidden layer's width is a multiple of 32: its blocks come in pairs)
+  const uint32_t kp0 = (uint32_t)sgpr((int)M.kpack[l][0]), kp1 = (uint32_t)sgpr((int)M.kpack[l][1]),
+                 kp2 = (uint32_t)sgpr((int)M.kpack[l][2]);
+  const int bb = sgpr((int)M.boff[l]);
   if constexpr (INPLACE) {
     h16x8 pend[NT][NC];
+    int fo = sgpr(M.foff[l][nob]);   // end of the layer; pairs run downwards
 #pragma unroll
     for (int kbo = KB - 1; kbo >= 0; --kbo) {
       if (2 * kbo < nob) {
+        const int ke0 = kend_packed(kp0, kp1, kp2, 2 * kbo), ke1 = kend_packed(kp0, kp1, kp2, 2 * kbo + 1);
+        const int f1 = fo - ke1, f0 = f1 - ke0;
+        fo = f0;
         f32x4 a0[NC], a1[NC];
         {
-          const f32x4 b0 = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
-          const f32x4 b1 = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
+          const f32x4 b0 = load_bias4(bias, bb + 32 * kbo + 4 * g);
+          const f32x4 b1 = load_bias4(bias, bb + 32 * kbo + 16 + 4 * g);
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        hidden_pair<KB, NT, NC, PREFETCH>(M, W, l, kbo, act, lane, a0, a1, kbo + 1, kbo + 2);
+        hidden_pair<KB, NT, NC, PREFETCH>(W, kbo, ke0, ke1, f0, f1, act, lane, a0, a1, kbo + 1, kbo + 2);
         if (kbo + 1 < KB && 2 * (kbo + 1) < nob) {
 #pragma unroll
           for (int i = 0; i < NT; ++i)
@@ -368,18 +379,22 @@ __device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __re
 #pragma unroll
       for (int c = 0; c < NC; ++c) act[i][c][0] = pend[i][c];
   } else {
+    // (the narrower networks that run out of place keep four waves per SIMD, which hide
+    // the table reads; there, direct reads measured faster than the packed words)
     h16x8 nxt[NT][NC][KB];
 #pragma unroll
     for (int kbo = 0; kbo < KB; ++kbo) {
       if (2 * kbo < nob) {
+        const int ke0 = sgpr(M.kend[l][2 * kbo]), ke1 = sgpr(M.kend[l][2 * kbo + 1]);
+        const int f0 = sgpr(M.foff[l][2 * kbo]), f1 = sgpr(M.foff[l][2 * kbo + 1]);
         f32x4 a0[NC], a1[NC];
         {
-          const f32x4 b0 = load_bias4(bias, M.boff[l] + 32 * kbo + 4 * g);
-          const f32x4 b1 = load_bias4(bias, M.boff[l] + 32 * kbo + 16 + 4 * g);
+          const f32x4 b0 = load_bias4(bias, bb + 32 * kbo + 4 * g);
+          const f32x4 b1 = load_bias4(bias, bb + 32 * kbo + 16 + 4 * g);
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        hidden_pair<KB, NT, NC, PREFETCH>(M, W, l, kbo, act, lane, a0, a1);
+        hidden_pair<KB, NT, NC, PREFETCH>(W, kbo, ke0, ke1, f0, f1, act, lane, a0, a1);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           h16x8 t[NT];
@@ -559,10 +574,12 @@ __device__ __forceinline__ void mlp_bf16(const MadeDev& M, const int32_t* lds, c
         ke = ke1;
       }
     } else {
+      // (four waves per SIMD: direct table reads, as in the out-of-place hidden layers)
+      const int l = M.L;
 #pragma unroll 1
       for (int ob = sgpr(ob_first); ob < nob; ++ob) {
         f32x4 acc[NC];
-        out_block<KB, NT, NC>(M, W, bias, act, ob, lane, acc);
+        out_block<KB, NT, NC>(W, bias, M.boff[l], act, ob, sgpr(M.kend[l][ob]), sgpr(M.foff[l][ob]), lane, acc);
         epi(ob, acc);
       }
     }
