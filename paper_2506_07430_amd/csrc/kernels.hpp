@@ -87,9 +87,9 @@ constexpr int eval_waves_bf16(int hmax, int nterms, int nc) {
   return nc == 1 ? (hmax <= 128 ? 16 : 8) : hmax * nterms <= 256 ? 8 : 4;
 }
 constexpr int kMaxEvalWavesBF16 = 16;
-// Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists and
-// the FP64 suffix sums of its per-orbital log2 probabilities.
-constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx) + (kMaxOrb + 1) * sizeof(double);
+// Per-wave LDS context of the fused BF16 kernels: the sample's occupied/virtual lists (the
+// FP64 suffix sums of its per-orbital log2 probabilities stay in registers, one per lane).
+constexpr size_t kWaveCtxBytesBF16 = sizeof(SampleCtx);
 // Input-expansion table of the fused BF16 kernels, in LDS after the wave contexts: entry v
 // holds the 4 fp16 values (bit j of v ? 1 : 0); two entries form the layer-0 operand of 8
 // input bits.

@@ -736,7 +736,6 @@ __global__ void __launch_bounds__(256) k_rows_bf16(RowsArgs P) {
 // ----------------------------------------------------------------------------- fused eval
 struct WaveCtxBF16 {
   SampleCtx c;
-  double sfx[kMaxOrb + 1];   // sum_{q >= p} log2 p_q(s_q) of the sample, sfx[n] = 0
 };
 static_assert(sizeof(WaveCtxBF16) == kWaveCtxBytesBF16, "per-wave LDS context size");
 
@@ -746,6 +745,7 @@ struct SampleState {
   int64_t b;
   uint64_t xs[NW];
   double sig_x, ed;
+  double sfx;   // lane q: sum_{p >= q} log2 p_p(s_p) of the sample (0 from the last orbital on)
   const double* Fs;
 };
 
@@ -834,8 +834,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t*
         const double u = __shfl_down(v, off);
         if (lane + off < 64) v += u;
       }
-      if (lane < n) wc.sfx[lane] = v;
-      if (lane == 0) wc.sfx[n] = 0.0;
+      st.sfx = v;   // lanes >= n - 1 sum nothing: 0
     }
     wave_sync_lds();
     st.sig_x = sigmoid64(P.zphi[b]);
@@ -860,6 +859,8 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t*
       for (int w = 0; w < NW; ++w) xo[w] = xs[w];
     }
     const int p0o = first_diff_orbital<NW>(xs, xo, n);
+    // the sample's part of this entry's dA, from the lane that holds orbital p0o
+    const double sfx_own = __shfl(st.sfx, min(p0o, 63));
     const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
     double dA_own = 0.0;
     float zp_own = 0.f;
@@ -917,7 +918,7 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t*
 #pragma unroll
         for (int cc = 1; cc < NC; ++cc)
           if (c == cc) { dsel = dA[cc]; zsel = zp[cc]; }
-        dA_own = dsel - wc.sfx[p0o];
+        dA_own = dsel - (p0o < n ? sfx_own : 0.0);
         zp_own = zsel;
       }
     }
