@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--pauli-samples", type=int, default=1024)
     ap.add_argument("--dedup-reps", type=int, default=5)
     ap.add_argument("--kpm-moments", type=int, default=64)
-    ap.add_argument("--connect-reps", type=int, default=3)
+    ap.add_argument("--connect-reps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size reference "
                          "for HBM byte counters)")

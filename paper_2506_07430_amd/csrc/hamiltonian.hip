@@ -154,12 +154,21 @@ __global__ void __launch_bounds__(256) k_connect_flat(SysDev S, const uint64_t* 
   __syncthreads();
   const size_t o = o0 + 2u * threadIdx.x;   // even
   if (o >= E) return;
-  const ListEntry<NW> r0 = flat_entry<NW>(S, c, b0, x, ediag, F, o);
   if (o + 1u >= E) {
-    store_entry<NW>(r0, o, xp, hval, sign, exc);
+    store_entry<NW>(flat_entry<NW>(S, c, b0, x, ediag, F, o), o, xp, hval, sign, exc);
     return;
   }
-  const ListEntry<NW> r1 = flat_entry<NW>(S, c, b0, x, ediag, F, o + 1u);
+  // the pair's sample words, single-excitation row and diagonal are read once; the second
+  // entry starts the next sample only when the first is a sample's last
+  const int64_t b = b0 + (o >= (size_t)(b0 + 1) * S.C ? 1 : 0);
+  const uint32_t t = (uint32_t)(o - (size_t)b * S.C);
+  uint64_t xv[NW];
+  load_x<NW>(x, b, xv);
+  const double* Fs = F + (size_t)b * (S.nSa + S.nSb);
+  const double ed = ediag[b];
+  const ListEntry<NW> r0 = list_entry<NW>(S, c[b - b0], xv, Fs, ed, t);
+  const ListEntry<NW> r1 = t + 1u < S.C ? list_entry<NW>(S, c[b - b0], xv, Fs, ed, t + 1u)
+                                        : flat_entry<NW>(S, c, b0, x, ediag, F, o + 1u);
   static_assert(NW == 1 || NW == 2, "one or two words per determinant");
   if constexpr (NW == 1) {
     const u64x2 y = {r0.y[0], r1.y[0]};
