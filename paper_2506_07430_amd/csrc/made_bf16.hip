@@ -630,8 +630,10 @@ constexpr double kLn2 = 0.6931471805599453094;
 // orbitals. The softmax runs over the occupations that keep both electron counts
 // reachable: alpha must be taken if cu < ta (= n_alpha - orbitals after p), may be
 // taken if cu < na (same for beta). Base 2 on the native exp2/log2 units (one rescale
-// to natural log per row, by the caller); the exponentials are taken unshifted unless
-// the log of their sum leaves (-99, 99).
+// to natural log per row, by the caller), shifted by the taken occupation's logit:
+// log2 p = -log2(sum over allowed s of 2^(y_s - y_taken)), where the taken term is 1, so
+// the sum is >= 1; it overflows only when p is below 2^-128, and then gives -inf, the
+// right limit for a ratio (that entry's amplitude is 0 to double precision).
 template <int NW>
 __device__ __forceinline__ float cond_log2p_step(RowCursor<NW>& rc, int ta, int tb, int na, int nb,
                                                  const f32x4& z) {
@@ -641,27 +643,16 @@ __device__ __forceinline__ float cond_log2p_step(RowCursor<NW>& rc, int ta, int 
   const bool ok0 = !a_must && !b_must, ok1 = a_may && !b_must;
   const bool ok2 = !a_must && b_may, ok3 = a_may && b_may;
   const float y0 = z[0] * kLog2e, y1 = z[1] * kLog2e, y2 = z[2] * kLog2e, y3 = z[3] * kLog2e;
-  const float e0 = ok0 ? __builtin_amdgcn_exp2f(y0) : 0.f;
-  const float e1 = ok1 ? __builtin_amdgcn_exp2f(y1) : 0.f;
-  const float e2 = ok2 ? __builtin_amdgcn_exp2f(y2) : 0.f;
-  const float e3 = ok3 ? __builtin_amdgcn_exp2f(y3) : 0.f;
-  const float sum = (e0 + e1) + (e2 + e3);
-  float lse = __builtin_amdgcn_logf(sum);
-  if (__builtin_expect(!(fabsf(lse) < 99.0f), 0)) {
-    float m = -INFINITY;
-    m = ok0 ? fmaxf(m, y0) : m;
-    m = ok1 ? fmaxf(m, y1) : m;
-    m = ok2 ? fmaxf(m, y2) : m;
-    m = ok3 ? fmaxf(m, y3) : m;
-    float t = (ok0 ? __builtin_amdgcn_exp2f(y0 - m) : 0.f) + (ok1 ? __builtin_amdgcn_exp2f(y1 - m) : 0.f) +
-              (ok2 ? __builtin_amdgcn_exp2f(y2 - m) : 0.f) + (ok3 ? __builtin_amdgcn_exp2f(y3 - m) : 0.f);
-    lse = m + __builtin_amdgcn_logf(t);
-  }
   const float y01 = (b8 & 1u) ? y1 : y0;
   const float y23 = (b8 & 1u) ? y3 : y2;
   const float ys = (b8 & 2u) ? y23 : y01;
+  const float e0 = ok0 ? __builtin_amdgcn_exp2f(y0 - ys) : 0.f;
+  const float e1 = ok1 ? __builtin_amdgcn_exp2f(y1 - ys) : 0.f;
+  const float e2 = ok2 ? __builtin_amdgcn_exp2f(y2 - ys) : 0.f;
+  const float e3 = ok3 ? __builtin_amdgcn_exp2f(y3 - ys) : 0.f;
+  const float sum = (e0 + e1) + (e2 + e3);
   cursor_advance4<NW>(rc, b8);
-  return ys - lse;
+  return -__builtin_amdgcn_logf(sum);
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
