@@ -25,7 +25,7 @@ CASES = [(1, 0, (0, 8191, -1), ("bf16",)), (1, 0, (0,), ("fp64",))] + \
     [(2, s, (0, -1), ("bf16",)) for s in range(8)] + [
     (3, 0, (0, 4095, -1), ("bf16",)),
     (3, 0, (0,), ("fp64",)),
-    (4, 0, (0, -1), ("bf16",)),
+    (4, 0, (0, 100, 200, 300, 400, 500, 600, 700, 800, -1), ("bf16",)),
     (4, 0, (0,), ("fp64",)),
 ]
 
