@@ -642,14 +642,14 @@ __device__ __forceinline__ float cond_log2p_step(RowCursor<NW>& rc, int ta, int 
   const bool b_must = rc.cd < tb, b_may = rc.cd < nb;
   const bool ok0 = !a_must && !b_must, ok1 = a_may && !b_must;
   const bool ok2 = !a_must && b_may, ok3 = a_may && b_may;
-  const float y0 = z[0] * kLog2e, y1 = z[1] * kLog2e, y2 = z[2] * kLog2e, y3 = z[3] * kLog2e;
-  const float y01 = (b8 & 1u) ? y1 : y0;
-  const float y23 = (b8 & 1u) ? y3 : y2;
-  const float ys = (b8 & 2u) ? y23 : y01;
-  const float e0 = ok0 ? __builtin_amdgcn_exp2f(y0 - ys) : 0.f;
-  const float e1 = ok1 ? __builtin_amdgcn_exp2f(y1 - ys) : 0.f;
-  const float e2 = ok2 ? __builtin_amdgcn_exp2f(y2 - ys) : 0.f;
-  const float e3 = ok3 ? __builtin_amdgcn_exp2f(y3 - ys) : 0.f;
+  // the taken logit in log2 units; each exponent is one fused multiply-add
+  const float z01 = (b8 & 1u) ? z[1] : z[0];
+  const float z23 = (b8 & 1u) ? z[3] : z[2];
+  const float ys = ((b8 & 2u) ? z23 : z01) * kLog2e;
+  const float e0 = ok0 ? __builtin_amdgcn_exp2f(__builtin_fmaf(z[0], kLog2e, -ys)) : 0.f;
+  const float e1 = ok1 ? __builtin_amdgcn_exp2f(__builtin_fmaf(z[1], kLog2e, -ys)) : 0.f;
+  const float e2 = ok2 ? __builtin_amdgcn_exp2f(__builtin_fmaf(z[2], kLog2e, -ys)) : 0.f;
+  const float e3 = ok3 ? __builtin_amdgcn_exp2f(__builtin_fmaf(z[3], kLog2e, -ys)) : 0.f;
   const float sum = (e0 + e1) + (e2 + e3);
   cursor_advance4<NW>(rc, b8);
   return -__builtin_amdgcn_logf(sum);
