@@ -257,10 +257,14 @@ __device__ __forceinline__ void out_block(const h16x8* __restrict__ W, const flo
 // otherwise), so that the k-blocks below kmin run without a test and those from kcap on are
 // dropped at compile time.
 // ke0, ke1: the blocks' k-ranges; f0, f1: their first fragments.
-template <int KB, int NT, int NC, bool PREFETCH>
+struct NoWork {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <int KB, int NT, int NC, bool PREFETCH, class Mid = NoWork>
 __device__ __forceinline__ void hidden_pair(const h16x8* __restrict__ W, int kbo, int ke0, int ke1, int f0, int f1,
                                             const h16x8 (&act)[NT][NC][KB], int lane, f32x4 (&a0)[NC],
-                                            f32x4 (&a1)[NC], int kmin = 1, int kcap = KB) {
+                                            f32x4 (&a1)[NC], int kmin = 1, int kcap = KB, Mid&& mid = Mid{}) {
   ke0 = min(ke0, kcap);
   ke1 = min(ke1, kcap);
   const h16x8* w0p = W + (size_t)f0 * 64 + lane;
@@ -274,6 +278,7 @@ __device__ __forceinline__ void hidden_pair(const h16x8* __restrict__ W, int kbo
       if (kb < kmin || (kb < kcap && kb < ke1)) w1b[0][j] = w1p[kb * 64];
       if (kb < kmin || (kb < kcap && kb < ke0)) w0b[0][j] = w0p[kb * 64];
     }
+    mid();   // VALU work of the caller that overlaps the first loads
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       __builtin_amdgcn_sched_barrier(0);
@@ -305,6 +310,7 @@ __device__ __forceinline__ void hidden_pair(const h16x8* __restrict__ W, int kbo
       }
     }
   } else {
+    mid();
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       // ke0 <= ke1 (degrees grow along the layer): one exit once block 1's range ends
@@ -343,7 +349,10 @@ __device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __re
                  kp2 = (uint32_t)sgpr((int)M.kpack[l][2]);
   const int bb = sgpr((int)M.boff[l]);
   if constexpr (INPLACE) {
+    // r0/r1: the products of the pair above, split (ReLU, fp16 terms) while the next pair's
+    // first weight loads are in flight; pend: that split, stored once the next pair is done
     h16x8 pend[NT][NC];
+    f32x4 r0[NC], r1[NC];
     int fo = sgpr(M.foff[l][nob]);   // end of the layer; pairs run downwards
 #pragma unroll
     for (int kbo = KB - 1; kbo >= 0; --kbo) {
@@ -358,26 +367,35 @@ __device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __re
 #pragma unroll
           for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
         }
-        hidden_pair<KB, NT, NC, PREFETCH>(W, kbo, ke0, ke1, f0, f1, act, lane, a0, a1, kbo + 1, kbo + 2);
-        if (kbo + 1 < KB && 2 * (kbo + 1) < nob) {
+        const bool above = kbo + 1 < KB && 2 * (kbo + 1) < nob;   // pair kbo + 1 exists
+        hidden_pair<KB, NT, NC, PREFETCH>(W, kbo, ke0, ke1, f0, f1, act, lane, a0, a1, kbo + 1, kbo + 2, [&] {
+          if (above) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              h16x8 t[NT];
+              split_relu<NT>(r0[c], r1[c], t);
+#pragma unroll
+              for (int i = 0; i < NT; ++i) pend[i][c] = t[i];
+            }
+          }
+        });
+        if (above) {
 #pragma unroll
           for (int i = 0; i < NT; ++i)
 #pragma unroll
             for (int c = 0; c < NC; ++c) act[i][c][kbo + 1 < KB ? kbo + 1 : 0] = pend[i][c];
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          h16x8 t[NT];
-          split_relu<NT>(a0[c], a1[c], t);
-#pragma unroll
-          for (int i = 0; i < NT; ++i) pend[i][c] = t[i];
-        }
+        for (int c = 0; c < NC; ++c) { r0[c] = a0[c]; r1[c] = a1[c]; }
       }
     }
 #pragma unroll
-    for (int i = 0; i < NT; ++i)
+    for (int c = 0; c < NC; ++c) {   // pair 0 (every layer has it)
+      h16x8 t[NT];
+      split_relu<NT>(r0[c], r1[c], t);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) act[i][c][0] = pend[i][c];
+      for (int i = 0; i < NT; ++i) act[i][c][0] = t[i];
+    }
   } else {
     // (the narrower networks that run out of place keep four waves per SIMD, which hide
     // the table reads; there, direct reads measured faster than the packed words)
