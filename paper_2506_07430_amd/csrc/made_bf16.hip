@@ -331,6 +331,60 @@ __device__ __forceinline__ void hidden_pair(const h16x8* __restrict__ W, int kbo
   }
 }
 
+// In-place hidden layer (see hidden_layer): pairs of output blocks from the highest down.
+// FULL: the layer has all KB pairs (nob == 2 KB).
+template <int KB, int NT, int NC, bool PREFETCH, bool FULL>
+__device__ __forceinline__ void hidden_inplace(const h16x8* __restrict__ W, const float* __restrict__ bias,
+                                               uint32_t kp0, uint32_t kp1, uint32_t kp2, int bb, int fo, int nob,
+                                               int g, int lane, h16x8 (&act)[NT][NC][KB]) {
+  // r0/r1: the products of the pair above, split (ReLU, fp16 terms) while the next pair's
+  // first weight loads are in flight; pend: that split, stored once the next pair is done
+  h16x8 pend[NT][NC];
+  f32x4 r0[NC], r1[NC];
+#pragma unroll
+  for (int kbo = KB - 1; kbo >= 0; --kbo) {
+    if (FULL || 2 * kbo < nob) {
+      const int ke0 = kend_packed(kp0, kp1, kp2, 2 * kbo), ke1 = kend_packed(kp0, kp1, kp2, 2 * kbo + 1);
+      const int f1 = fo - ke1, f0 = f1 - ke0;
+      fo = f0;
+      f32x4 a0[NC], a1[NC];
+      {
+        const f32x4 b0 = load_bias4(bias, bb + 32 * kbo + 4 * g);
+        const f32x4 b1 = load_bias4(bias, bb + 32 * kbo + 16 + 4 * g);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
+      }
+      const bool above = kbo + 1 < KB && (FULL || 2 * (kbo + 1) < nob);   // pair kbo + 1 exists
+      hidden_pair<KB, NT, NC, PREFETCH>(W, kbo, ke0, ke1, f0, f1, act, lane, a0, a1, kbo + 1, kbo + 2, [&] {
+        if (above) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            h16x8 t[NT];
+            split_relu<NT>(r0[c], r1[c], t);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) pend[i][c] = t[i];
+          }
+        }
+      });
+      if (above) {
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) act[i][c][kbo + 1 < KB ? kbo + 1 : 0] = pend[i][c];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { r0[c] = a0[c]; r1[c] = a1[c]; }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {   // pair 0 (every layer has it)
+    h16x8 t[NT];
+    split_relu<NT>(r0[c], r1[c], t);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) act[i][c][0] = t[i];
+  }
+}
+
 // Hidden layer l >= 1. Without INPLACE the outputs go to a second activation array. With
 // INPLACE they overwrite the inputs: pairs run from the last to the first, and the
 // result of pair j is held back until pair j - 1 is done, then stored in k-slot j. This
@@ -349,53 +403,12 @@ __device__ __forceinline__ void hidden_layer(const MadeDev& M, const h16x8* __re
                  kp2 = (uint32_t)sgpr((int)M.kpack[l][2]);
   const int bb = sgpr((int)M.boff[l]);
   if constexpr (INPLACE) {
-    // r0/r1: the products of the pair above, split (ReLU, fp16 terms) while the next pair's
-    // first weight loads are in flight; pend: that split, stored once the next pair is done
-    h16x8 pend[NT][NC];
-    f32x4 r0[NC], r1[NC];
-    int fo = sgpr(M.foff[l][nob]);   // end of the layer; pairs run downwards
-#pragma unroll
-    for (int kbo = KB - 1; kbo >= 0; --kbo) {
-      if (2 * kbo < nob) {
-        const int ke0 = kend_packed(kp0, kp1, kp2, 2 * kbo), ke1 = kend_packed(kp0, kp1, kp2, 2 * kbo + 1);
-        const int f1 = fo - ke1, f0 = f1 - ke0;
-        fo = f0;
-        f32x4 a0[NC], a1[NC];
-        {
-          const f32x4 b0 = load_bias4(bias, bb + 32 * kbo + 4 * g);
-          const f32x4 b1 = load_bias4(bias, bb + 32 * kbo + 16 + 4 * g);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) { a0[c] = b0; a1[c] = b1; }
-        }
-        const bool above = kbo + 1 < KB && 2 * (kbo + 1) < nob;   // pair kbo + 1 exists
-        hidden_pair<KB, NT, NC, PREFETCH>(W, kbo, ke0, ke1, f0, f1, act, lane, a0, a1, kbo + 1, kbo + 2, [&] {
-          if (above) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              h16x8 t[NT];
-              split_relu<NT>(r0[c], r1[c], t);
-#pragma unroll
-              for (int i = 0; i < NT; ++i) pend[i][c] = t[i];
-            }
-          }
-        });
-        if (above) {
-#pragma unroll
-          for (int i = 0; i < NT; ++i)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) act[i][c][kbo + 1 < KB ? kbo + 1 : 0] = pend[i][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) { r0[c] = a0[c]; r1[c] = a1[c]; }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {   // pair 0 (every layer has it)
-      h16x8 t[NT];
-      split_relu<NT>(r0[c], r1[c], t);
-#pragma unroll
-      for (int i = 0; i < NT; ++i) act[i][c][0] = t[i];
-    }
+    // a layer of the full width has every pair: no test per pair (a runtime test there costs
+    // register moves at every join)
+    if (nob == 2 * KB)
+      hidden_inplace<KB, NT, NC, PREFETCH, true>(W, bias, kp0, kp1, kp2, bb, sgpr(M.foff[l][nob]), nob, g, lane, act);
+    else
+      hidden_inplace<KB, NT, NC, PREFETCH, false>(W, bias, kp0, kp1, kp2, bb, sgpr(M.foff[l][nob]), nob, g, lane, act);
   } else {
     // (the narrower networks that run out of place keep four waves per SIMD, which hide
     // the table reads; there, direct reads measured faster than the packed words)
