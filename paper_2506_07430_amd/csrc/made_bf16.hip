@@ -692,9 +692,9 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int wave_min(int v) {
+__device__ __forceinline__ int row_min(int v) {   // least over the lane's 16-lane row
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+  for (int off = 8; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
   return v;
 }
 
@@ -883,7 +883,9 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t*
     const int p0o = first_diff_orbital<NW>(xs, xo, n);
     // the sample's part of this entry's dA, from the lane that holds orbital p0o
     const double sfx_own = __shfl(st.sfx, min(p0o, 63));
-    const int ob_first = sgpr(min(wave_min(p0o) >> 2, ob_phi));
+    // the first changed orbital, least over each 16-lane row (a tile's rows): output blocks
+    // below a tile's least one hold only orbitals that all its rows share with x
+    const int p0_row = row_min(p0o);
     double dA_own = 0.0;
     float zp_own = 0.f;
     // ---- network on entries 16 NC h .. 16 NC (h + 1) - 1 (not unrolled: one copy of the
@@ -902,6 +904,10 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t*
       double dA[NC];
       float zp[NC];
       RowCursor<NW> rc[NC];
+      int ob_first = __builtin_amdgcn_readlane(p0_row, 16 * NC * h);
+#pragma unroll
+      for (int c = 1; c < NC; ++c) ob_first = min(ob_first, __builtin_amdgcn_readlane(p0_row, 16 * NC * h + 16 * c));
+      ob_first = sgpr(min(ob_first >> 2, ob_phi));
       const int pfirst = min(4 * ob_first + g, n - 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
