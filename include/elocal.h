@@ -384,11 +384,13 @@ elocal_status elocal_tune(elocal_t h, int param, int64_t value);
  * ELOCAL_INFO_GRID blocks, ELOCAL_INFO_GROUPS groups per work item, ELOCAL_INFO_WAVES waves
  * per block, ELOCAL_INFO_COLS tiles per pass, ELOCAL_INFO_MAX_WAVES the waves per block the
  * kernel variant is built for, ELOCAL_INFO_ITEMS work items, ELOCAL_INFO_LDS_BYTES LDS per
- * block.
+ * block, ELOCAL_INFO_INPLACE 1 when the hidden layers are updated in place (one activation
+ * array in registers; chosen when every hidden o-block pair j reads k-blocks j + 1 to j + 2
+ * only), else 0.
  */
 enum {
   ELOCAL_INFO_GRID = 0, ELOCAL_INFO_GROUPS = 1, ELOCAL_INFO_WAVES = 2, ELOCAL_INFO_COLS = 3,
-  ELOCAL_INFO_MAX_WAVES = 4, ELOCAL_INFO_ITEMS = 5, ELOCAL_INFO_LDS_BYTES = 6
+  ELOCAL_INFO_MAX_WAVES = 4, ELOCAL_INFO_ITEMS = 5, ELOCAL_INFO_LDS_BYTES = 6, ELOCAL_INFO_INPLACE = 7
 };
 int64_t elocal_launch_info(elocal_t h, const elocal_ansatz* a, int64_t B, int what);
 

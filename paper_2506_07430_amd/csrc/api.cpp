@@ -1488,6 +1488,7 @@ int64_t elocal_launch_info(elocal_t h, const elocal_ansatz* a, int64_t B, int wh
       return G.precision == ELOCAL_BF16 ? eval_waves_bf16(G.hmax, G.nterms, p.cols) : p.waves;
     case ELOCAL_INFO_ITEMS: return p.n_items;
     case ELOCAL_INFO_LDS_BYTES: return (int64_t)p.lds;
+    case ELOCAL_INFO_INPLACE: return p.inplace ? 1 : 0;
   }
   fail(ELOCAL_E_INVALID, "unknown launch-info query %d", what);
   return -1;

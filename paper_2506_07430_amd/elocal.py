@@ -292,7 +292,7 @@ class Hamiltonian:
 
     def launch_info(self, ansatz: Ansatz, B: int) -> dict:
         """The launch shape elocal_eval would use for this ansatz and batch size."""
-        keys = ("grid", "groups", "waves", "cols", "max_waves", "items", "lds_bytes")
+        keys = ("grid", "groups", "waves", "cols", "max_waves", "items", "lds_bytes", "inplace")
         out = {}
         for i, k in enumerate(keys):
             v = lib().elocal_launch_info(self._h, ansatz.ref(), int(B), i)

@@ -158,18 +158,24 @@ def test_eval_bf16_c0():
 @pytest.mark.parametrize("precision", [elocal.BF16, elocal.BF16X3])
 @pytest.mark.parametrize("n,na,nb,widths", [(2, 1, 1, (32,)), (3, 1, 2, (32,)), (5, 2, 1, (32,)),
                                              (5, 0, 3, (64,)), (12, 6, 5, (64, 32)), (33, 8, 9, (32, 32)),
-                                             (17, 8, 8, (256,)), (64, 3, 2, (64,)), (10, 4, 5, (96, 160))])
+                                             (17, 8, 8, (256,)), (64, 3, 2, (64,)), (10, 4, 5, (96, 160)),
+                                             (33, 10, 9, (256, 224)), (40, 14, 14, (256, 256, 224))])
 def test_eval_bf16_shapes(n, na, nb, widths, precision):
     """Shapes at the packing's edges: a single orbital with logits (n = 2), the phase row
     alone in an output block (n = 5), an empty spin block, the word boundary (n = 33),
     the width-256 kernels, the largest n and widths that are not powers of two (96, 160:
-    odd numbers of weight chunks); local energies and log psi of samples drawn
+    odd numbers of weight chunks), width-256 networks whose last hidden layer is narrower
+    (224: the in-place layers without every block pair, beside a full-width one); local energies and log psi of samples drawn
     from the ansatz (uniformly drawn determinants of the sparse 64-orbital sector have
     ratios psi(x')/psi(x) up to e^21, whose FP32 log-softmax rounding alone exceeds the bar)."""
     p = synth.random_problem(n, na, nb, widths, seed=300 + n + na, n_chol=4, decay=5.0, samples=1)
-    _, th_or = theta_for(p.theta, precision)
+    th_dev, th_or = theta_for(p.theta, precision)
     x = ansatz_samples(p, min(5, math.comb(n, na) * math.comb(n, nb)), seed=n, theta=th_or)
-    el, lp, th = _eval(p, x, precision)
+    ham = make_ham(p)
+    if max(widths) == 256 and len(widths) > 1 and precision == elocal.BF16:
+        # width-256 networks with hidden-to-hidden layers update them in place
+        assert ham.launch_info(elocal.Ansatz(widths, th_dev, precision), x.shape[0])["inplace"] == 1
+    el, lp, th = _eval(p, x, precision, ham)
     ref = _oracle_eloc(p, x, th)
     A, phi = oen.log_psi(th, x, n, na, nb, widths)
     err = np.abs(el - ref)
