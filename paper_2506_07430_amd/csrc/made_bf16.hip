@@ -928,10 +928,10 @@ __device__ __forceinline__ void eval_item_bf16(const EvalArgs& P, const int32_t*
             dA[c] += (double)d;     // sum over p >= p0 of log2 p(x'); x's part is subtracted below
           }
         }
-        if (ob == ob_phi && g == g_phi) {
+        // the phase row is the output layer's last row (block ob_phi, the last one run): the
+        // value the last block leaves in lane group g_phi is the phase logit
 #pragma unroll
-          for (int c = 0; c < NC; ++c) zp[c] = a[c][0];
-        }
+        for (int c = 0; c < NC; ++c) zp[c] = a[c][0];
       });
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
